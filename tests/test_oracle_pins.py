@@ -1,0 +1,373 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test ties one part of the oracle to the mathematics or to values worked
+out by hand from the paper's definitions (Sec. 4.3 Eqs. 4-6, Sec. 4.4.1 Eq. 9,
+Sec. 4.4.2, Sec. 5.2.1-5.2.2): exact rational arithmetic for the cell index,
+brute-force enumeration, closed forms of the DFT, a library FFT, a direct sum
+over visibilities, invariants, the dot-product test and finite differences.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+C = O.C_LIGHT
+
+
+def _golden():
+    with open(os.path.join(HERE, "golden", "hand_worked_4x4.json")) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- cell index
+def test_uv_scale_exact_unit_case():
+    # N dx = 1 and nu = c give exactly one cell per metre (Eq. 9).
+    s = O.uv_scale([C], 4, 0.25)
+    assert s[0] == 1.0
+
+
+def test_uv_scale_matches_rational_arithmetic():
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        n = int(rng.choice([64, 128, 180, 1024, 2048]))
+        dx = float(rng.uniform(1e-5, 2e-2))
+        nu = float(rng.uniform(5e7, 3.5e8))
+        s = O.uv_scale([nu], n, dx)[0]
+        # correctly rounded at each of the three IEEE steps
+        ndx = float(Fraction(n) * Fraction(dx))
+        prod = float(Fraction(nu) * Fraction(ndx))
+        ref = float(Fraction(prod) / Fraction(C))
+        assert s == ref
+        # and within 3 ulp of the exact value nu N dx / c
+        exact = Fraction(nu) * Fraction(n) * Fraction(dx) / Fraction(C)
+        assert abs(Fraction(s) - exact) <= 3 * Fraction(math.ulp(s))
+
+
+def test_cell_index_is_rint_of_one_product():
+    rng = np.random.default_rng(2)
+    u = rng.uniform(-3000, 3000, 4000)
+    v = rng.uniform(-3000, 3000, 4000)
+    s = O.uv_scale([185e6], 1024, 8.3e-5)[0]
+    iu, iv, keep = O.cell_index(u, v, s, 1024)
+    for k in range(0, 4000, 7):
+        xu = float(Fraction(float(u[k])) * Fraction(float(s)))   # correctly rounded product
+        xv = float(Fraction(float(v[k])) * Fraction(float(s)))
+        ru, rv = round(xu), round(xv)                            # Python round: half to even
+        kept = abs(ru) < 512 and abs(rv) < 512
+        assert bool(keep[k]) == kept
+        if kept:
+            assert (iu[k], iv[k]) == (ru, rv)
+
+
+def test_cell_index_ties_and_edges():
+    g = _golden()["rounding"]
+    n = g["N"]
+    s = O.uv_scale([C], n, 1.0 / n)[0]
+    assert s == 1.0
+    u = np.array(g["u_m"])
+    iu, iv, keep = O.cell_index(u, np.zeros_like(u), s, n)
+    for k, e in enumerate(g["expect_iu"]):
+        if e is None:
+            assert not keep[k]
+        else:
+            assert keep[k] and iu[k] == e
+    # odd symmetry: the mirror of a kept cell is the cell of the negated baseline
+    iu2, _, keep2 = O.cell_index(-u, np.zeros_like(u), s, n)
+    assert np.array_equal(keep, keep2)
+    assert np.array_equal(iu[keep], -iu2[keep2])
+
+
+def test_flags_drop_baselines():
+    u = np.array([1.0, 2.0, 3.0])
+    iu, iv, keep = O.cell_index(u, u, 1.0, 16, flagged=np.array([0, 1, 0], np.uint8))
+    assert keep.tolist() == [True, False, True]
+
+
+# ---------------------------------------------------------------- gridding
+def _random_problem(rng, n, nb, scale=None):
+    s = scale if scale is not None else 1.0
+    u = rng.uniform(-n / 2, n / 2, nb) / s
+    v = rng.uniform(-n / 2, n / 2, nb) / s
+    vis = rng.normal(size=nb) + 1j * rng.normal(size=nb)
+    return u, v, vis
+
+
+def test_counts_brute_force_and_symmetry():
+    rng = np.random.default_rng(3)
+    n = 16
+    u, v, vis = _random_problem(rng, n, 300)
+    iu, iv, keep = O.cell_index(u, v, 1.0, n)
+    S, cnt = O.grid(vis, iu, iv, keep, n)
+    bf = np.zeros((n, n), dtype=np.int64)
+    for b in range(len(u)):
+        if keep[b]:
+            bf[int(iv[b]) % n, int(iu[b]) % n] += 1
+            bf[(-int(iv[b])) % n, (-int(iu[b])) % n] += 1
+    assert np.array_equal(cnt, bf)
+    assert cnt.sum() == 2 * keep.sum()
+    mirror = np.roll(np.flip(cnt, (0, 1)), (1, 1), axis=(0, 1))   # n[-k]
+    assert np.array_equal(cnt, mirror)
+    # the grid is Hermitian: S[-k] = conj(S[k])
+    Sm = np.roll(np.flip(S, (0, 1)), (1, 1), axis=(0, 1))
+    assert np.allclose(S, np.conj(Sm), atol=1e-12)
+    # the Nyquist row and column stay empty (symmetric keep range)
+    assert cnt[n // 2, :].sum() == 0 and cnt[:, n // 2].sum() == 0
+
+
+def test_uniform_equals_natural_when_cells_are_single():
+    n = 32
+    # distinct cells, none at a mirror of another: u = 1..8, v = 2u
+    u = np.arange(1, 9, dtype=float)
+    v = 2 * u - 3
+    vis = np.exp(1j * u)
+    iu, iv, keep = O.cell_index(u, v, 1.0, n)
+    S, cnt = O.grid(vis, iu, iv, keep, n)
+    assert cnt.max() == 1
+    Gn, Wn = O.weight(S, cnt, O.NATURAL)
+    Gu, Wu = O.weight(S, cnt, O.UNIFORM)
+    assert np.allclose(Gn, Gu) and Wn == Wu == 16
+
+
+def test_uniform_weight_sum_counts_cells():
+    rng = np.random.default_rng(4)
+    n = 8
+    u, v, vis = _random_problem(rng, n, 60)
+    iu, iv, keep = O.cell_index(u, v, 1.0, n)
+    S, cnt = O.grid(vis, iu, iv, keep, n)
+    G, W = O.weight(S, cnt, O.UNIFORM)
+    assert W == np.count_nonzero(cnt)
+    occ = cnt > 0
+    assert np.allclose(G[occ] * cnt[occ], S[occ])
+
+
+# ---------------------------------------------------------------- FFT
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 8, 9, 12, 15, 16, 30, 45, 64, 90, 128, 180])
+def test_fft_last_axis_vs_library(n):
+    rng = np.random.default_rng(n)
+    x = rng.normal(size=(3, n)) + 1j * rng.normal(size=(3, n))
+    inv = O.fft_last_axis(x, +1)
+    fwd = O.fft_last_axis(x, -1)
+    assert np.allclose(inv, np.fft.ifft(x, axis=-1) * n, rtol=0, atol=1e-11 * max(1, n))
+    assert np.allclose(fwd, np.fft.fft(x, axis=-1), rtol=0, atol=1e-11 * max(1, n))
+
+
+@pytest.mark.parametrize("n", [4, 6, 16, 30, 64])
+def test_fft2_closed_forms(n):
+    # delta at k0 -> exp(+2 pi i k0.q / N)
+    k0 = (1, n // 3)
+    G = np.zeros((n, n), complex)
+    G[k0] = 1.0
+    R = O.fft2(G, +1)
+    q = np.arange(n)
+    expect = np.exp(2j * np.pi * ((k0[0] * q[:, None] + k0[1] * q[None, :]) % n) / n)
+    assert np.allclose(R, expect, atol=1e-12)
+    # constant 1 -> N^2 at the origin only
+    R1 = O.fft2(np.ones((n, n), complex), +1)
+    e1 = np.zeros((n, n))
+    e1[0, 0] = n * n
+    assert np.allclose(R1, e1, atol=1e-9)
+
+
+@pytest.mark.parametrize("n", [8, 12, 180])
+def test_fft2_recursive_matrix_library_agree(n):
+    rng = np.random.default_rng(7)
+    G = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    a = O.fft2(G, +1)
+    b = O.dft2_matrix(G, +1)
+    c = np.fft.ifft2(G) * n * n
+    scale = np.abs(c).max()
+    assert np.abs(a - b).max() <= 1e-12 * scale
+    assert np.abs(a - c).max() <= 1e-12 * scale
+    # Parseval: sum |R|^2 = N^2 sum |G|^2
+    assert np.isclose((np.abs(a) ** 2).sum(), n * n * (np.abs(G) ** 2).sum(), rtol=1e-12)
+
+
+def test_fft2_1024_vs_library():
+    rng = np.random.default_rng(8)
+    G = np.zeros((1024, 1024), complex)
+    idx = rng.integers(0, 1024, size=(2, 2000))
+    G[idx[0], idx[1]] = rng.normal(size=2000) + 1j * rng.normal(size=2000)
+    a = O.fft2(G, +1)
+    c = np.fft.ifft2(G) * 1024 * 1024
+    assert np.abs(a - c).max() <= 1e-12 * np.abs(c).max()
+
+
+# ---------------------------------------------------------------- whole image
+def test_hand_worked_examples():
+    g = _golden()
+    for case in g["cases"]:
+        u = np.array(case["u_m"])
+        v = np.array(case["v_m"])
+        vis = np.array(case["vis_re"]) + 1j * np.array(case["vis_im"])
+        for norm, key in ((O.NORM_NONE, "image_raw"), (O.NORM_WEIGHTS, "image_norm")):
+            r = O.image_one(vis, u, v, C, 4, 0.25, 4, case["weighting"], norm)
+            assert np.allclose(r["image"], np.array(case[key], float), atol=1e-12), case["name"]
+            assert r["W"] == case["W"]
+        nz = [[int(a), int(b), int(r["counts"][a, b])] for a, b in zip(*np.nonzero(r["counts"]))]
+        assert sorted(nz) == sorted(case["counts_nonzero"])
+
+
+@pytest.mark.parametrize("weighting", [0, 1])
+@pytest.mark.parametrize("n,m", [(8, 8), (12, 6), (16, 10)])
+def test_image_equals_direct_sum(weighting, n, m):
+    rng = np.random.default_rng(10 + n + weighting)
+    nb = 25
+    u, v, vis = _random_problem(rng, n, nb, scale=0.77)
+    g = 0.9 + 0.2 * rng.random(6) + 0.1j * rng.normal(size=6)
+    a1 = rng.integers(0, 6, nb)
+    a2 = rng.integers(0, 6, nb)
+    s = O.uv_scale([C], n, 0.77 / n)[0]
+    iu, iv, keep = O.cell_index(u, v, s, n)
+    vp = O.apply_gains(vis, g, a1, a2)
+    for norm in (O.NORM_NONE, O.NORM_WEIGHTS):
+        r = O.image_one(vis, u, v, C, n, 0.77 / n, m, weighting, norm, gains=g, ant1=a1, ant2=a2)
+        d = O.direct_image(vp, iu, iv, keep, n, m, weighting, norm)
+        assert np.allclose(r["image"], d, atol=1e-11 * max(1.0, np.abs(d).max()))
+        rm = O.image_one(vis, u, v, C, n, 0.77 / n, m, weighting, norm, gains=g, ant1=a1,
+                         ant2=a2, fft="matrix")
+        assert np.allclose(r["image"], rm["image"], atol=1e-11 * max(1.0, np.abs(d).max()))
+
+
+def _on_cell_point_source(n, a, b, flux, nb=120, seed=0):
+    """Baselines exactly on cell centres, point source at pixel offset (a, b)."""
+    rng = np.random.default_rng(seed)
+    dx = 1.0 / n               # N dx = 1, and nu = c -> s = 1
+    iu = rng.integers(-n // 2 + 1, n // 2, nb).astype(float)
+    iv = rng.integers(-n // 2 + 1, n // 2, nb).astype(float)
+    l, m = a * dx, b * dx
+    # Eq. 5 with a point source: V = S exp(-2 pi i (u l + v m)), u, v in wavelengths
+    vis = flux * np.exp(-2j * np.pi * (iu * l + iv * m))
+    return iu, iv, vis, dx
+
+
+@pytest.mark.parametrize("weighting", [0, 1])
+def test_point_source_lands_on_its_pixel(weighting):
+    n = 32
+    for (a, b) in [(0, 0), (3, -5), (-7, 2)]:
+        u, v, vis, dx = _on_cell_point_source(n, a, b, 4.5, seed=abs(a * 7 + b))
+        r = O.image_one(vis, u, v, C, n, dx, n, weighting, O.NORM_WEIGHTS)
+        img = r["image"]
+        pk = np.unravel_index(np.argmax(img), img.shape)
+        # row follows m (v), column follows l (u); phase centre at [N/2][N/2]
+        assert pk == (n // 2 + b, n // 2 + a)
+        assert np.isclose(img[pk], 4.5, rtol=1e-12)
+
+
+def test_phase_centre_source_is_centred_and_symmetric():
+    n = 16
+    u, v, vis, dx = _on_cell_point_source(n, 0, 0, 2.0, seed=5)
+    img = O.image_one(vis, u, v, C, n, dx, n, 0, O.NORM_WEIGHTS)["image"]
+    assert np.isclose(img[n // 2, n // 2], 2.0, rtol=1e-13)
+    # centro-symmetric about the phase centre: I[N/2 + d] = I[N/2 - d]
+    core = img[1:, 1:]
+    assert np.allclose(core, core[::-1, ::-1], atol=1e-12)
+
+
+def test_image_sum_and_centre_identities():
+    rng = np.random.default_rng(11)
+    n = 16
+    u, v, vis = _random_problem(rng, n, 40)
+    iu, iv, keep = O.cell_index(u, v, 1.0, n)
+    S, cnt = O.grid(vis, iu, iv, keep, n)
+    for wt in (0, 1):
+        G, W = O.weight(S, cnt, wt)
+        R = O.fft2(G, +1)
+        # Hermitian grid -> real transform
+        assert np.abs(R.imag).max() <= 1e-12 * np.abs(R).max()
+        # image sum equals N^2 times the weighted visibility sum at the uv origin
+        assert np.isclose(R.real.sum(), n * n * G[0, 0].real, atol=1e-9)
+        # centre value equals the sum of the weighted grid = 2 sum_b w_b Re V_b
+        k = np.flatnonzero(keep)
+        wb = 1.0 if wt == 0 else 1.0 / cnt[np.mod(iv[k], n), np.mod(iu[k], n)]
+        assert np.isclose(R[0, 0].real, np.sum(2 * wb * np.real(vis[k])), atol=1e-10)
+
+
+# ---------------------------------------------------------------- adjoint
+def _small_case(seed=12, n=16, nb=40, n_ant=8, weighting=0):
+    rng = np.random.default_rng(seed)
+    u, v, vis = _random_problem(rng, n, nb, scale=1.3)
+    a1 = rng.integers(0, n_ant, nb)
+    a2 = (a1 + 1 + rng.integers(0, n_ant - 1, nb)) % n_ant
+    g = 1 + 0.05 * rng.normal(size=n_ant) + 0.05j * rng.normal(size=n_ant)
+    return u, v, vis, a1, a2, g
+
+
+@pytest.mark.parametrize("weighting", [0, 1])
+@pytest.mark.parametrize("norm", [0, 1])
+def test_adjoint_dot_product(weighting, norm):
+    n, m = 16, 10
+    u, v, vis, a1, a2, g = _small_case(weighting=weighting)
+    dx = 1.3 / n
+    rng = np.random.default_rng(99)
+    Ibar = rng.normal(size=(m, m))
+    # the image is linear in V' ; check <I(V'), Ibar> = <V', gamma'> with gains off
+    img = O.image_one(vis, u, v, C, n, dx, m, weighting, norm)["image"]
+    gp, _ = O.adjoint_one(Ibar, vis, u, v, C, n, dx, weighting, norm)
+    lhs = np.sum(img * Ibar)
+    rhs = np.sum(gp.real * vis.real + gp.imag * vis.imag)
+    assert np.isclose(lhs, rhs, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("weighting", [0, 1])
+def test_adjoint_finite_differences(weighting):
+    n, m = 16, 12
+    u, v, vis, a1, a2, g = _small_case(seed=21, weighting=weighting)
+    dx = 1.3 / n
+    rng = np.random.default_rng(5)
+    target = rng.normal(size=(m, m))
+
+    def loss(vv, gg):
+        img = O.image_one(vv, u, v, C, n, dx, m, weighting, 1, gains=gg, ant1=a1, ant2=a2)["image"]
+        return float(np.sum((img - target) ** 2))
+
+    img = O.image_one(vis, u, v, C, n, dx, m, weighting, 1, gains=g, ant1=a1, ant2=a2)["image"]
+    Ibar = 2 * (img - target)
+    vg, gg = O.adjoint_one(Ibar, vis, u, v, C, n, dx, weighting, 1, gains=g, ant1=a1, ant2=a2)
+
+    def fd(f, x, k, part):
+        h = 1e-6 * max(1.0, abs(x[k]))
+        d = h if part == 0 else 1j * h
+        xp = x.copy(); xp[k] += d
+        xm = x.copy(); xm[k] -= d
+        return (f(xp) - f(xm)) / (2 * h)
+
+    for k in range(len(g)):
+        for part in (0, 1):
+            num = fd(lambda gg_: loss(vis, gg_), g, k, part)
+            ana = gg[k].real if part == 0 else gg[k].imag
+            assert abs(num - ana) <= 1e-6 * max(1.0, abs(ana))
+    for k in range(0, len(vis), 3):
+        for part in (0, 1):
+            num = fd(lambda vv: loss(vv, g), vis, k, part)
+            ana = vg[k].real if part == 0 else vg[k].imag
+            assert abs(num - ana) <= 1e-6 * max(1.0, abs(ana))
+
+
+# ---------------------------------------------------------------- precision form
+def test_dequantize_half_and_bfloat16():
+    import torch
+    rng = np.random.default_rng(13)
+    x = rng.uniform(-1, 1, 1000)
+    sig = 3.25
+    q16 = (x).astype(np.float16)
+    d = O.dequantize(q16, q16, sig)
+    # fp16 round-to-nearest: relative step 2^-11 in the normal range
+    nz = np.abs(x) > 2 ** -14
+    assert np.all(np.abs(d.real[nz] / sig - x[nz]) <= 2 ** -11 * np.abs(x[nz]))
+    bf = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16)
+    bits = bf.view(torch.int16).numpy().view(np.uint16)
+    d2 = O.dequantize(bits, bits, sig)
+    assert np.allclose(d2.real, bf.double().numpy() * sig, rtol=0, atol=0)
+    assert np.all(np.abs(d2.real / sig - x) <= 2 ** -8 * np.abs(x) + 1e-300)
+
+
+def test_cost_table_arithmetic():
+    # the FFT operation-count model of the cost table: N^2 log2 N^2
+    assert round(O.fft_flops_estimate(180)) == 485472
+    assert O.fft_flops_estimate(1024) == 1024 ** 2 * 20
