@@ -1,0 +1,174 @@
+/*
+ * blink.h - C ABI of the MI355X (gfx950) dirty-imaging library libblink.so.
+ *
+ * For every (timestep, channel) image the library grids the visibilities of
+ * all baselines onto an N x N uv grid and applies the 2D inverse FFT; the real
+ * part, shifted so that the phase centre sits at the image centre, is the
+ * dirty image (Sokolowski et al., "High-Time Resolution GPU Imager for FRB
+ * searches at low radio frequencies": Sec. 4.3 Eqs. 4-6, Sec. 4.4 Eqs. 7-9,
+ * Sec. 5.2.1-5.2.2, Sec. 5.2.4).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - blink_problem and blink_inputs are host structs, read during the call
+ *   only. Every array they (or the calls) point to is DEVICE memory, owned by
+ *   the caller; the library never allocates, frees or synchronises.
+ * - Scratch memory comes from a caller-provided device workspace of at least
+ *   blink_workspace_size() bytes, 256-byte aligned. Its contents on entry are
+ *   irrelevant; it must not be shared by calls that may run concurrently.
+ * - Work is enqueued on the caller's HIP stream `stream`. Nothing inside a
+ *   call blocks the host, so calls may be captured into a HIP graph.
+ * - Arrays are C-contiguous, row-major. blink_c32 is {float re, im}, the
+ *   layout of torch.complex64 / std::complex<float>.
+ * - Argument errors are detected on the host before anything is enqueued and
+ *   leave every output untouched. A failed kernel launch returns BLINK_E_HIP.
+ *   Faults during execution surface at the caller's next synchronisation.
+ * - No mutable global state: calls are thread-safe.
+ *
+ * Geometry and the readings of the paper used throughout
+ * ------------------------------------------------------
+ * - uvw_m[t][b] = (u, v, w) of baseline b at timestep t in metres; w is
+ *   ignored (coplanar array phased to zenith, Sec. 4.3 Eq. 5).
+ * - Cells per metre of channel c: s_c = (freq_hz[c] * (N * pixscale)) / c0 with
+ *   c0 = 299792458 m/s, evaluated in IEEE double in that order (Eq. 9 gives
+ *   the cell du = 1/(N dx) wavelengths; Sec. 5.2.4 computes the channel
+ *   frequency and wavelength in double).
+ * - Cell of baseline b: i_u = rint(u * s_c), i_v = rint(v * s_c) (one double
+ *   product, round half to even). The baseline is kept iff it is not flagged,
+ *   u and v are finite, |i_u| < N/2 and |i_v| < N/2; kept baselines are
+ *   counted at (i_v mod N, i_u mod N) with value V' and at the mirror cell
+ *   with conj(V') (the input holds each antenna pair once).
+ * - V' = gains[ant1[b]] * conj(gains[ant2[b]]) * V when gains are given
+ *   (post-correlation calibration, Sec. 4.2 (ii)); for FP16/BF16 storage
+ *   V = (float(q_re) + i float(q_im)) * vis_scale[c].
+ * - Weighting (Sec. 4.4.2): NATURAL cell value = sum, W = sum of counts;
+ *   UNIFORM cell value = sum / count, W = number of occupied cells.
+ * - Image: unnormalised inverse transform exp(+2 pi i (k.q)/N), real part,
+ *   FFT shift (Sec. 5.2.2), times 1/W when norm = BLINK_NORM_WEIGHTS (W = 0
+ *   gives zeros), then the central M x M cutout. Layout [m][l]: row follows
+ *   v (m), column follows u (l), phase centre at [M/2][M/2].
+ */
+#ifndef BLINK_H
+#define BLINK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* blink_stream_t;   /* the same handle as hipStream_t */
+
+typedef struct { float re, im; } blink_c32;
+
+typedef enum {
+  BLINK_OK = 0,
+  BLINK_E_ARG = -1,          /* null required pointer, bad enum, non-finite or <= 0 pixscale */
+  BLINK_E_SIZE = -2,         /* negative sizes, odd N or M, M > N, element count overflow   */
+  BLINK_E_UNSUPPORTED = -3,  /* N without a compiled transform plan, or a combination not built */
+  BLINK_E_WORKSPACE = -4,    /* workspace null, misaligned or smaller than required          */
+  BLINK_E_HIP = -5           /* a HIP launch failed (hipGetLastError after the enqueue)       */
+} blink_status;
+
+typedef enum { BLINK_NATURAL = 0, BLINK_UNIFORM = 1 } blink_weighting;
+typedef enum { BLINK_VIS_C64 = 0, BLINK_VIS_F16 = 1, BLINK_VIS_BF16 = 2 } blink_vis_type;
+typedef enum { BLINK_NORM_NONE = 0, BLINK_NORM_WEIGHTS = 1 } blink_norm;
+typedef enum {
+  BLINK_CALL_GRID = 0,       /* blink_grid            */
+  BLINK_CALL_IMAGE = 1,      /* blink_image_batch     */
+  BLINK_CALL_ADJOINT = 2     /* blink_degrid_adjoint  */
+} blink_call;
+
+typedef struct {
+  int32_t n_time;        /* T: timesteps in the cube                                  */
+  int32_t n_chan;        /* C: channels                                               */
+  int32_t n_bl;          /* B: baselines (each antenna pair once)                     */
+  int32_t n_ant;         /* A: antennas (gains length; may be 0 without gains)        */
+  int32_t grid_n;        /* N: even, one of the sizes reported by blink_supported_n   */
+  int32_t out_n;         /* M: even, M <= N; central M x M cutout of the N x N image   */
+  double  pixscale;      /* dx: pixel size in direction-cosine units (> 0, finite)     */
+  int32_t weighting;     /* blink_weighting                                           */
+  int32_t norm;          /* blink_norm                                                */
+  int32_t vis_type;      /* blink_vis_type                                            */
+  int32_t chunk_images;  /* images per internal chunk; 0 = library default            */
+} blink_problem;
+
+typedef struct {          /* device pointers; the optional ones may be NULL            */
+  const void*      vis;       /* [T][C][B] blink_c32, or [T][C][B][2] f16 / bf16 pairs  */
+  const float*     vis_scale; /* [C] dequantisation scale; required for f16 / bf16      */
+  const double*    uvw_m;     /* [T][B][3] metres                                       */
+  const double*    freq_hz;   /* [C] Hz                                                  */
+  const uint8_t*   flags;     /* [T][B] nonzero = flagged for every channel, or NULL    */
+  const int32_t*   ant1;      /* [B] antenna of the first input (required with gains)    */
+  const int32_t*   ant2;      /* [B] antenna of the second input                         */
+  const blink_c32* gains;     /* [A] per-antenna complex gains, or NULL                  */
+} blink_inputs;
+
+/* Human-readable name of a status code (static string). */
+const char* blink_status_string(blink_status s);
+
+/* 1 if a transform plan for length n is compiled in, else 0. */
+int32_t blink_supported_n(int32_t n);
+
+/* Bytes of workspace that `call` needs for problem `p` (0 on invalid input). */
+size_t blink_workspace_size(const blink_problem* p, int32_t call);
+
+/*
+ * blink_grid: the gridding step alone (Sec. 5.2.1 steps 1-3, Sec. 4.4.2).
+ * Writes, for every image i = t*C + c:
+ *   grid[i][k_v][k_u]  blink_c32, the WEIGHTED grid that the inverse FFT
+ *                      consumes (natural: cell sums; uniform: sum / count),
+ *                      DC at [0][0], both the cell and its mirror filled;
+ *   counts[i][k_v][k_u] int32 visibilities per cell (NULL to skip);
+ *   weight_sum[i]      float W (NULL to skip);
+ *   n_dropped[i]       int32 unflagged baselines outside the grid or with
+ *                      non-finite u, v (NULL to skip).
+ * grid is [T*C][N][N]; out_n and norm are ignored.
+ */
+blink_status blink_grid(const blink_problem* p, const blink_inputs* in,
+                        blink_c32* grid, int32_t* counts, float* weight_sum,
+                        int32_t* n_dropped, void* workspace, size_t ws_bytes,
+                        blink_stream_t stream);
+
+/*
+ * blink_fft2d: batched unnormalised 2D C2C transform of [batch][n][n]
+ * complex arrays: out[q] = sum_k in[k] exp(sign * 2 pi i (k_v q_v + k_u q_u) / n)
+ * (sign = +1 is the inverse transform of Sec. 5.2.2, -1 the forward one).
+ * in == out is allowed; otherwise the buffers must not overlap. No workspace.
+ */
+blink_status blink_fft2d(const blink_c32* in, blink_c32* out, int32_t batch,
+                         int32_t n, int32_t sign, blink_stream_t stream);
+
+/*
+ * blink_image_batch: the whole path, visibilities -> dirty images, for all
+ * T*C images of the cube (Sec. 5.2.4 "layers"): images [T*C][M][M] float,
+ * weight_sum [T*C] float W (NULL to skip). Ragged batches (different flag
+ * counts per timestep) need no padding.
+ */
+blink_status blink_image_batch(const blink_problem* p, const blink_inputs* in,
+                               float* images, float* weight_sum,
+                               void* workspace, size_t ws_bytes,
+                               blink_stream_t stream);
+
+/*
+ * blink_degrid_adjoint: gradients of a real loss L through blink_image_batch,
+ * given image_grad = dL/d(images) [T*C][M][M] float:
+ *   vis_grad[t][c][b]  = dL/dRe V + i dL/dIm V   (blink_c32, all baselines;
+ *                        zero for flagged or dropped ones);
+ *   gain_grad[a]       = dL/dRe g + i dL/dIm g   (NULL to skip; needs gains,
+ *                        ant1, ant2).
+ * The map V -> image is linear (W and the counts depend only on geometry and
+ * flags), so this is the exact adjoint: zero-pad, 1/W, inverse shift, forward
+ * transform, cell weight, gather at +k and -k (degridding). C64 only.
+ */
+blink_status blink_degrid_adjoint(const blink_problem* p, const blink_inputs* in,
+                                  const float* image_grad, blink_c32* vis_grad,
+                                  blink_c32* gain_grad, void* workspace,
+                                  size_t ws_bytes, blink_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLINK_H */

@@ -1,0 +1,274 @@
+"""ctypes binding of libblink.so: the C ABI of include/blink.h with torch tensors.
+
+Argument marshalling only: shapes and dtypes are checked, device pointers and
+the current HIP stream are handed to the library, which enqueues all the work.
+There is no fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libblink.so")
+
+NATURAL, UNIFORM = 0, 1
+NORM_NONE, NORM_WEIGHTS = 0, 1
+VIS_C64, VIS_F16, VIS_BF16 = 0, 1, 2
+CALL_GRID, CALL_IMAGE, CALL_ADJOINT = 0, 1, 2
+
+STATUS = {0: "BLINK_OK", -1: "BLINK_E_ARG", -2: "BLINK_E_SIZE", -3: "BLINK_E_UNSUPPORTED",
+          -4: "BLINK_E_WORKSPACE", -5: "BLINK_E_HIP"}
+
+# every symbol include/blink.h declares
+EXPORTS = ("blink_status_string", "blink_supported_n", "blink_workspace_size", "blink_grid",
+           "blink_fft2d", "blink_image_batch", "blink_degrid_adjoint")
+
+
+class BlinkError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(code, code)} ({status_string(code)})")
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n_time", ctypes.c_int32), ("n_chan", ctypes.c_int32), ("n_bl", ctypes.c_int32),
+                ("n_ant", ctypes.c_int32), ("grid_n", ctypes.c_int32), ("out_n", ctypes.c_int32),
+                ("pixscale", ctypes.c_double), ("weighting", ctypes.c_int32),
+                ("norm", ctypes.c_int32), ("vis_type", ctypes.c_int32),
+                ("chunk_images", ctypes.c_int32)]
+
+
+class Inputs(ctypes.Structure):
+    _fields_ = [("vis", ctypes.c_void_p), ("vis_scale", ctypes.c_void_p), ("uvw_m", ctypes.c_void_p),
+                ("freq_hz", ctypes.c_void_p), ("flags", ctypes.c_void_p), ("ant1", ctypes.c_void_p),
+                ("ant2", ctypes.c_void_p), ("gains", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str | None = None):
+    """Load libblink.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libblink.so not built: {p} is missing (run __graft_entry__.build())")
+    lib = ctypes.CDLL(p)
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    P, I = ctypes.POINTER(Problem), ctypes.POINTER(Inputs)
+    lib.blink_status_string.argtypes = [i32]
+    lib.blink_status_string.restype = ctypes.c_char_p
+    lib.blink_supported_n.argtypes = [i32]
+    lib.blink_supported_n.restype = i32
+    lib.blink_workspace_size.argtypes = [P, i32]
+    lib.blink_workspace_size.restype = sz
+    lib.blink_grid.argtypes = [P, I, vp, vp, vp, vp, vp, sz, vp]
+    lib.blink_grid.restype = i32
+    lib.blink_fft2d.argtypes = [vp, vp, i32, i32, i32, vp]
+    lib.blink_fft2d.restype = i32
+    lib.blink_image_batch.argtypes = [P, I, vp, vp, vp, sz, vp]
+    lib.blink_image_batch.restype = i32
+    lib.blink_degrid_adjoint.argtypes = [P, I, vp, vp, vp, vp, sz, vp]
+    lib.blink_degrid_adjoint.restype = i32
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def status_string(code: int) -> str:
+    try:
+        return load_library().blink_status_string(int(code)).decode()
+    except RuntimeError:
+        return "library not loaded"
+
+
+def supported_n(n: int) -> bool:
+    return bool(load_library().blink_supported_n(int(n)))
+
+
+# ---------------------------------------------------------------- helpers
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t, name, dtype=None, shape=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(code, what):
+    if code != 0:
+        raise BlinkError(code, what)
+
+
+def make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n=None, weighting=NATURAL,
+                 norm=NORM_WEIGHTS, gains=None, chunk_images=0) -> Problem:
+    if vis.dtype == torch.complex64:
+        T, C, B = vis.shape
+        vt = VIS_C64
+    elif vis.dtype in (torch.float16, torch.bfloat16):
+        T, C, B, two = vis.shape
+        if two != 2:
+            raise ValueError("half-precision visibilities must be [T][C][B][2]")
+        vt = VIS_F16 if vis.dtype == torch.float16 else VIS_BF16
+    else:
+        raise ValueError(f"unsupported visibility dtype {vis.dtype}")
+    return Problem(n_time=T, n_chan=C, n_bl=B, n_ant=0 if gains is None else gains.shape[0],
+                   grid_n=grid_n, out_n=grid_n if out_n is None else out_n,
+                   pixscale=float(pixscale), weighting=int(weighting), norm=int(norm),
+                   vis_type=vt, chunk_images=int(chunk_images))
+
+
+def make_inputs(p: Problem, vis, uvw_m, freq_hz, flags=None, vis_scale=None, ant1=None,
+                ant2=None, gains=None):
+    T, C, B = p.n_time, p.n_chan, p.n_bl
+    _dev(vis, "vis")
+    _dev(uvw_m, "uvw_m", torch.float64, (T, B, 3))
+    _dev(freq_hz, "freq_hz", torch.float64, (C,))
+    _dev(flags, "flags", torch.uint8, (T, B))
+    _dev(vis_scale, "vis_scale", torch.float32, (C,))
+    _dev(ant1, "ant1", torch.int32, (B,))
+    _dev(ant2, "ant2", torch.int32, (B,))
+    _dev(gains, "gains", torch.complex64)
+    keep = (vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains)
+    inp = Inputs(vis=_ptr(vis), vis_scale=_ptr(vis_scale), uvw_m=_ptr(uvw_m), freq_hz=_ptr(freq_hz),
+                 flags=_ptr(flags), ant1=_ptr(ant1), ant2=_ptr(ant2), gains=_ptr(gains))
+    return inp, keep
+
+
+def workspace(p: Problem, call: int, device) -> torch.Tensor:
+    n = load_library().blink_workspace_size(ctypes.byref(p), int(call))
+    if n == 0:
+        return torch.empty(0, dtype=torch.uint8, device=device)
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------- calls
+def image_batch(vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None, weighting=NATURAL,
+                norm=NORM_WEIGHTS, flags=None, vis_scale=None, ant1=None, ant2=None, gains=None,
+                chunk_images=0, images=None, weight_sum=None, ws=None, stream=None):
+    """Dirty images [T*C][M][M] float32 of the cube (blink_image_batch)."""
+    lib = load_library()
+    p = make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, weighting, norm, gains, chunk_images)
+    inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains)
+    n_img, M = p.n_time * p.n_chan, p.out_n
+    if images is None:
+        images = torch.empty((n_img, M, M), dtype=torch.float32, device=vis.device)
+    _dev(images, "images", torch.float32, (n_img, M, M))
+    _dev(weight_sum, "weight_sum", torch.float32, (n_img,))
+    if ws is None:
+        ws = workspace(p, CALL_IMAGE, vis.device)
+    code = lib.blink_image_batch(ctypes.byref(p), ctypes.byref(inp), _ptr(images), _ptr(weight_sum),
+                                 _ptr(ws) if ws.numel() else None, ws.numel(), _stream(stream))
+    _check(code, "blink_image_batch")
+    return images
+
+
+def grid(vis, uvw_m, freq_hz, *, grid_n, pixscale, weighting=NATURAL, flags=None, vis_scale=None,
+         ant1=None, ant2=None, gains=None, counts=True, chunk_images=0, stream=None):
+    """(weighted grid [T*C][N][N] c64, counts int32 or None, W float32, n_dropped int32)."""
+    lib = load_library()
+    p = make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, grid_n, weighting, NORM_NONE, gains,
+                     chunk_images)
+    inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains)
+    n_img, N, dev = p.n_time * p.n_chan, grid_n, vis.device
+    g = torch.empty((n_img, N, N), dtype=torch.complex64, device=dev)
+    c = torch.empty((n_img, N, N), dtype=torch.int32, device=dev) if counts else None
+    w = torch.empty((n_img,), dtype=torch.float32, device=dev)
+    d = torch.empty((n_img,), dtype=torch.int32, device=dev)
+    ws = workspace(p, CALL_GRID, dev)
+    code = lib.blink_grid(ctypes.byref(p), ctypes.byref(inp), _ptr(g), _ptr(c), _ptr(w), _ptr(d),
+                          _ptr(ws) if ws.numel() else None, ws.numel(), _stream(stream))
+    _check(code, "blink_grid")
+    return g, c, w, d
+
+
+def fft2d(x, sign=+1, out=None, stream=None):
+    """Batched unnormalised 2D C2C transform of [batch][n][n] complex64 (blink_fft2d)."""
+    lib = load_library()
+    _dev(x, "x", torch.complex64)
+    if x.dim() != 3 or x.shape[1] != x.shape[2]:
+        raise ValueError("x must be [batch][n][n]")
+    if out is None:
+        out = torch.empty_like(x)
+    _dev(out, "out", torch.complex64, tuple(x.shape))
+    code = lib.blink_fft2d(_ptr(x), _ptr(out), int(x.shape[0]), int(x.shape[1]), int(sign),
+                           _stream(stream))
+    _check(code, "blink_fft2d")
+    return out
+
+
+def degrid_adjoint(image_grad, vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None,
+                   weighting=NATURAL, norm=NORM_WEIGHTS, flags=None, ant1=None, ant2=None,
+                   gains=None, want_gain_grad=True, chunk_images=0, stream=None):
+    """(vis_grad [T][C][B] c64, gain_grad [A] c64 or None) of a loss with dL/dimages = image_grad."""
+    lib = load_library()
+    p = make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, weighting, norm, gains, chunk_images)
+    inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, None, ant1, ant2, gains)
+    n_img, M = p.n_time * p.n_chan, p.out_n
+    _dev(image_grad, "image_grad", torch.float32, (n_img, M, M))
+    vg = torch.empty(vis.shape, dtype=torch.complex64, device=vis.device)
+    gg = None
+    if gains is not None and want_gain_grad:
+        gg = torch.empty(gains.shape, dtype=torch.complex64, device=vis.device)
+    ws = workspace(p, CALL_ADJOINT, vis.device)
+    code = lib.blink_degrid_adjoint(ctypes.byref(p), ctypes.byref(inp), _ptr(image_grad), _ptr(vg),
+                                    _ptr(gg), _ptr(ws) if ws.numel() else None, ws.numel(),
+                                    _stream(stream))
+    _check(code, "blink_degrid_adjoint")
+    return vg, gg
+
+
+class BlinkImage(torch.autograd.Function):
+    """Differentiable dirty imaging: images = blink_image_batch(g[a1] conj(g[a2]) V).
+
+    Gradients flow to the complex64 visibilities and the per-antenna gains
+    through the hand-written adjoint (degridding + forward transforms).
+    """
+
+    @staticmethod
+    def forward(ctx, vis, gains, uvw_m, freq_hz, ant1, ant2, flags, grid_n, pixscale, out_n,
+                weighting, norm):
+        ctx.save_for_backward(vis, gains, uvw_m, freq_hz, ant1, ant2, flags)
+        ctx.cfg = (grid_n, pixscale, out_n, weighting, norm)
+        return image_batch(vis, uvw_m, freq_hz, grid_n=grid_n, pixscale=pixscale, out_n=out_n,
+                           weighting=weighting, norm=norm, flags=flags, ant1=ant1, ant2=ant2,
+                           gains=gains)
+
+    @staticmethod
+    def backward(ctx, grad_images):
+        vis, gains, uvw_m, freq_hz, ant1, ant2, flags = ctx.saved_tensors
+        grid_n, pixscale, out_n, weighting, norm = ctx.cfg
+        vg, gg = degrid_adjoint(grad_images.contiguous().float(), vis, uvw_m, freq_hz,
+                                grid_n=grid_n, pixscale=pixscale, out_n=out_n,
+                                weighting=weighting, norm=norm, flags=flags, ant1=ant1,
+                                ant2=ant2, gains=gains,
+                                want_gain_grad=gains is not None and ctx.needs_input_grad[1])
+        return (vg if ctx.needs_input_grad[0] else None, gg, None, None, None, None, None,
+                None, None, None, None, None)
+
+
+def blink_image(vis, gains, uvw_m, freq_hz, ant1, ant2, *, grid_n, pixscale, out_n=None,
+                weighting=NATURAL, norm=NORM_WEIGHTS, flags=None):
+    """Functional form of BlinkImage."""
+    return BlinkImage.apply(vis, gains, uvw_m, freq_hz, ant1, ant2, flags, grid_n, pixscale,
+                            grid_n if out_n is None else out_n, weighting, norm)

@@ -1,0 +1,418 @@
+// Host side of libblink.so: argument validation, workspace layout and the
+// launch sequences behind the C ABI declared in include/blink.h.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "blink.h"
+#include "blink_kernels.hpp"
+
+using namespace blink;
+
+namespace {
+
+constexpr int SORT_RUN_SMALL = 1024;
+constexpr int SORT_RUN = 8192;
+constexpr int MAX_GRID_Y = 65535;
+constexpr size_t CHUNK_TARGET_BYTES = size_t(96) << 20;   // half-spectrum bytes per chunk
+
+bool n_supported(int n) {
+  switch (n) {
+    case 8: case 12: case 16: case 32: case 64: case 128: case 180:
+    case 256: case 512: case 1024: case 2048: case 4096:
+      return true;
+    default:
+      return false;
+  }
+}
+
+inline size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Work {
+  unsigned long long* key[2];
+  int* idx[2];
+  int* counters;      // [2T]: n_unflagged then n_valid
+  double* su;
+  double* sv;
+  int* perm;
+  int* bnd;
+  int* wacc;
+  int* kacc;
+  float2* half;
+  float2* gamma;
+  float2* pacc;
+};
+
+int default_chunk(const blink_problem* p, int call, long long n_img) {
+  if (p->chunk_images > 0) return (int)std::min<long long>(p->chunk_images, std::max<long long>(n_img, 1));
+  long long per = 1;
+  if (call != BLINK_CALL_GRID) per = (long long)(p->grid_n / 2) * p->out_n * 8;
+  long long c = std::max<long long>(1, (long long)CHUNK_TARGET_BYTES / per);
+  c = std::min<long long>(c, std::max<long long>(n_img, 1));
+  return (int)std::min<long long>(c, MAX_GRID_Y);
+}
+
+// Lays out the workspace (base may be null to only size it).
+size_t carve(const blink_problem* p, int call, int chunk, char* base, Work* w) {
+  const size_t T = (size_t)p->n_time, B = (size_t)p->n_bl, N = (size_t)p->grid_n;
+  const size_t M = (size_t)p->out_n;
+  size_t o = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* r = base ? base + o : nullptr;
+    o += al(bytes);
+    return r;
+  };
+  Work x{};
+  x.key[0] = (unsigned long long*)take(T * B * 8);
+  x.key[1] = (unsigned long long*)take(T * B * 8);
+  x.idx[0] = (int*)take(T * B * 4);
+  x.idx[1] = (int*)take(T * B * 4);
+  x.counters = (int*)take(2 * T * 4);
+  x.su = (double*)take(T * B * 8);
+  x.sv = (double*)take(T * B * 8);
+  x.perm = (int*)take(T * B * 4);
+  x.bnd = (int*)take((size_t)chunk * (N + 2) * 4);
+  x.wacc = (int*)take((size_t)chunk * 4);
+  x.kacc = (int*)take((size_t)chunk * 4);
+  if (call == BLINK_CALL_IMAGE || call == BLINK_CALL_ADJOINT)
+    x.half = (float2*)take((size_t)chunk * (N / 2) * M * 8);
+  if (call == BLINK_CALL_ADJOINT) {
+    x.gamma = (float2*)take((size_t)chunk * B * 8);
+    x.pacc = (float2*)take(B * 8);
+  }
+  if (w) *w = x;
+  return o;
+}
+
+blink_status validate_problem(const blink_problem* p, int call) {
+  if (!p) return BLINK_E_ARG;
+  if (p->n_time < 0 || p->n_chan < 0 || p->n_bl < 0 || p->n_ant < 0) return BLINK_E_SIZE;
+  if (!(p->pixscale > 0.0) || !isfinite(p->pixscale)) return BLINK_E_ARG;
+  if (p->weighting != BLINK_NATURAL && p->weighting != BLINK_UNIFORM) return BLINK_E_ARG;
+  if (p->norm != BLINK_NORM_NONE && p->norm != BLINK_NORM_WEIGHTS) return BLINK_E_ARG;
+  if (p->vis_type < BLINK_VIS_C64 || p->vis_type > BLINK_VIS_BF16) return BLINK_E_ARG;
+  if (p->chunk_images < 0) return BLINK_E_ARG;
+  if (call < BLINK_CALL_GRID || call > BLINK_CALL_ADJOINT) return BLINK_E_ARG;
+  if (p->grid_n < 2 || (p->grid_n & 1)) return BLINK_E_SIZE;
+  if (call != BLINK_CALL_GRID) {
+    if (p->out_n < 2 || (p->out_n & 1) || p->out_n > p->grid_n) return BLINK_E_SIZE;
+  }
+  const long long T = p->n_time, C = p->n_chan, B = p->n_bl, N = p->grid_n;
+  if (T * C > INT32_MAX || T * B > INT32_MAX) return BLINK_E_SIZE;
+  if ((double)T * C * B > 9.0e18 || (double)T * C * N * N > 9.0e18) return BLINK_E_SIZE;
+  if (!n_supported(p->grid_n)) return BLINK_E_UNSUPPORTED;
+  if (call == BLINK_CALL_ADJOINT && p->vis_type != BLINK_VIS_C64) return BLINK_E_UNSUPPORTED;
+  return BLINK_OK;
+}
+
+blink_status validate_inputs(const blink_problem* p, const blink_inputs* in) {
+  if (!in) return BLINK_E_ARG;
+  const long long n_img = (long long)p->n_time * p->n_chan;
+  if (n_img == 0 || p->n_bl == 0) return BLINK_OK;
+  if (!in->vis || !in->uvw_m || !in->freq_hz) return BLINK_E_ARG;
+  if (p->vis_type != BLINK_VIS_C64 && !in->vis_scale) return BLINK_E_ARG;
+  if (in->gains && (!in->ant1 || !in->ant2 || p->n_ant < 1)) return BLINK_E_ARG;
+  return BLINK_OK;
+}
+
+blink_status check_ws(const blink_problem* p, int call, void* ws, size_t ws_bytes, int* chunk) {
+  const long long n_img = (long long)p->n_time * p->n_chan;
+  *chunk = default_chunk(p, call, n_img);
+  const size_t need = carve(p, call, *chunk, nullptr, nullptr);
+  if (need == 0) return BLINK_OK;
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) return BLINK_E_WORKSPACE;
+  return BLINK_OK;
+}
+
+blink_status launched() {
+  return hipGetLastError() == hipSuccess ? BLINK_OK : BLINK_E_HIP;
+}
+
+inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+// per-timestep order of the usable baselines by u (metres)
+void run_sort(const blink_problem* p, const blink_inputs* in, const Work& w, hipStream_t st) {
+  const int T = p->n_time, B = p->n_bl;
+  hipLaunchKernelGGL(k_sort_init, dim3(cdiv(2LL * T, 256)), dim3(256), 0, st, w.counters, 2 * T);
+  if (B == 0 || T == 0) return;
+  SortArgs s{};
+  s.T = T; s.B = B;
+  s.uvw = in->uvw_m; s.flags = in->flags;
+  s.key[0] = w.key[0]; s.key[1] = w.key[1];
+  s.idx[0] = w.idx[0]; s.idx[1] = w.idx[1];
+  s.n_unflagged = w.counters; s.n_valid = w.counters + T;
+  s.su = w.su; s.sv = w.sv; s.perm = w.perm;
+  const int run = B <= SORT_RUN_SMALL ? SORT_RUN_SMALL : SORT_RUN;
+  for (int t0 = 0; t0 < T; t0 += MAX_GRID_Y) {
+    const int nt = std::min(MAX_GRID_Y, T - t0);
+    s.t0 = t0;
+    if (run == SORT_RUN_SMALL)
+      hipLaunchKernelGGL((k_sort_run<SORT_RUN_SMALL>), dim3(1, nt), dim3(1024), 0, st, s);
+    else
+      hipLaunchKernelGGL((k_sort_run<SORT_RUN>), dim3(cdiv(B, SORT_RUN), nt), dim3(1024), 0, st, s);
+    int src = 0;
+    for (long long wdt = run; wdt < B; wdt *= 2) {
+      hipLaunchKernelGGL(k_merge, dim3(cdiv(B, 256), nt), dim3(256), 0, st, s, (int)wdt, src);
+      src ^= 1;
+    }
+    hipLaunchKernelGGL(k_sort_finish, dim3(cdiv(B, 256), nt), dim3(256), 0, st, s, src);
+  }
+}
+
+ImgArgs make_args(const blink_problem* p, const blink_inputs* in, const Work& w) {
+  ImgArgs a{};
+  a.T = p->n_time; a.C = p->n_chan; a.B = p->n_bl; a.N = p->grid_n; a.M = p->out_n;
+  a.weighting = p->weighting; a.norm = p->norm; a.vis_type = p->vis_type;
+  a.ndx = (double)p->grid_n * p->pixscale;
+  a.vis = in->vis; a.vis_scale = in->vis_scale; a.freq = in->freq_hz;
+  a.ant1 = in->ant1; a.ant2 = in->ant2;
+  a.gains = reinterpret_cast<const float2*>(in->gains);
+  a.n_ant = p->n_ant;
+  a.su = w.su; a.sv = w.sv; a.perm = w.perm;
+  a.n_unflagged = w.counters; a.n_valid = w.counters + p->n_time;
+  a.bnd = w.bnd; a.wacc = w.wacc; a.kacc = w.kacc;
+  a.half = w.half; a.gamma = w.gamma; a.pacc = w.pacc;
+  return a;
+}
+
+template <int N>
+blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t st) {
+  const long long n_img = (long long)p->n_time * p->n_chan;
+  const bool uni = p->weighting == BLINK_UNIFORM;
+  const size_t lds1 = Cols<N>::lds_bytes(uni);
+  for (long long i0 = 0; i0 < n_img; i0 += chunk) {
+    const int n = (int)std::min<long long>(chunk, n_img - i0);
+    a.img0 = (int)i0; a.nimg = n;
+    hipLaunchKernelGGL(k_bounds, dim3(n), dim3(256), 0, st, a);
+    const dim3 g1(cdiv(N / 2, Cols<N>::CPW), n);
+    if (uni)
+      hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, true>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
+    else
+      hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, false>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
+    const dim3 g2(cdiv(p->out_n / 2, Rows<N>::PPW), n);
+    hipLaunchKernelGGL((k_rows<N>), g2, dim3(Rows<N>::THREADS), Rows<N>::LDS, st, a);
+  }
+  return launched();
+}
+
+template <int N>
+blink_status grid_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t st) {
+  const long long n_img = (long long)p->n_time * p->n_chan;
+  const bool uni = p->weighting == BLINK_UNIFORM;
+  const size_t lds1 = Cols<N>::lds_bytes(true);
+  for (long long i0 = 0; i0 < n_img; i0 += chunk) {
+    const int n = (int)std::min<long long>(chunk, n_img - i0);
+    a.img0 = (int)i0; a.nimg = n;
+    hipLaunchKernelGGL(k_bounds, dim3(n), dim3(256), 0, st, a);
+    const dim3 g1(cdiv(N, Cols<N>::CPW), n);
+    if (uni)
+      hipLaunchKernelGGL((k_grid_cols<N, MODE_GRID, true>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
+    else
+      hipLaunchKernelGGL((k_grid_cols<N, MODE_GRID, false>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
+    if (a.weight_sum || a.n_dropped)
+      hipLaunchKernelGGL(k_grid_finish, dim3(cdiv(n, 256)), dim3(256), 0, st, a);
+  }
+  return launched();
+}
+
+template <int N>
+blink_status adjoint_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t st) {
+  const long long n_img = (long long)p->n_time * p->n_chan;
+  const bool uni = p->weighting == BLINK_UNIFORM;
+  if (a.gains)
+    hipLaunchKernelGGL(k_fill2, dim3(cdiv(a.B, 256)), dim3(256), 0, st, a.pacc, (size_t)a.B);
+  for (long long i0 = 0; i0 < n_img; i0 += chunk) {
+    const int n = (int)std::min<long long>(chunk, n_img - i0);
+    a.img0 = (int)i0; a.nimg = n;
+    hipLaunchKernelGGL(k_bounds, dim3(n), dim3(256), 0, st, a);
+    const dim3 g1(cdiv(N / 2, Cols<N>::CPW), n);
+    const size_t ldsw = uni ? (size_t)Cols<N>::CPW * N * sizeof(int) : 0;
+    if (uni)
+      hipLaunchKernelGGL((k_weights<N, true>), g1, dim3(Cols<N>::THREADS), ldsw, st, a);
+    else
+      hipLaunchKernelGGL((k_weights<N, false>), g1, dim3(Cols<N>::THREADS), ldsw, st, a);
+    const dim3 g2(cdiv(p->out_n / 2, Rows<N>::PPW), n);
+    hipLaunchKernelGGL((k_rows_adj<N>), g2, dim3(Rows<N>::THREADS), Rows<N>::LDS, st, a);
+    const size_t ng = (size_t)n * a.B;
+    hipLaunchKernelGGL(k_fill2, dim3(cdiv((long long)ng, 256)), dim3(256), 0, st, a.gamma, ng);
+    const size_t lds1 = Cols<N>::lds_bytes(uni);
+    if (uni)
+      hipLaunchKernelGGL((k_cols_adj<N, true>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
+    else
+      hipLaunchKernelGGL((k_cols_adj<N, false>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
+    hipLaunchKernelGGL(k_adj_finish, dim3(cdiv(a.B, 256)), dim3(256), 0, st, a);
+  }
+  if (a.gains && a.gain_grad)
+    hipLaunchKernelGGL(k_gain_grad, dim3(p->n_ant), dim3(256), 0, st, a);
+  return launched();
+}
+
+template <int N>
+blink_status fft2d_n(const float2* in, float2* out, int batch, int sign, hipStream_t st) {
+  const long long rows = (long long)batch * N;
+  constexpr long long ROWS_PER_LAUNCH = 1LL << 30;
+  for (long long r0 = 0; r0 < rows; r0 += ROWS_PER_LAUNCH) {
+    const long long nr = std::min<long long>(rows - r0, ROWS_PER_LAUNCH);
+    const dim3 g(cdiv(nr, Fft2<N>::VPW));
+    if (sign > 0)
+      hipLaunchKernelGGL((k_fft_rows<N, +1>), g, dim3(Fft2<N>::THREADS), Fft2<N>::LDS, st, in + r0 * N, out + r0 * N, (int)nr);
+    else
+      hipLaunchKernelGGL((k_fft_rows<N, -1>), g, dim3(Fft2<N>::THREADS), Fft2<N>::LDS, st, in + r0 * N, out + r0 * N, (int)nr);
+  }
+  for (long long b0 = 0; b0 < batch; b0 += MAX_GRID_Y) {
+    const int nb = (int)std::min<long long>(MAX_GRID_Y, batch - b0);
+    const dim3 g(cdiv(N, Fft2<N>::VPW), nb);
+    float2* d = out + (size_t)b0 * N * N;
+    if (sign > 0)
+      hipLaunchKernelGGL((k_fft_cols<N, +1>), g, dim3(Fft2<N>::THREADS), Fft2<N>::LDS, st, d);
+    else
+      hipLaunchKernelGGL((k_fft_cols<N, -1>), g, dim3(Fft2<N>::THREADS), Fft2<N>::LDS, st, d);
+  }
+  return launched();
+}
+
+#define BLINK_DISPATCH_N(n, CALL)                                    \
+  switch (n) {                                                       \
+    case 8: return CALL(8);                                          \
+    case 12: return CALL(12);                                        \
+    case 16: return CALL(16);                                        \
+    case 32: return CALL(32);                                        \
+    case 64: return CALL(64);                                        \
+    case 128: return CALL(128);                                      \
+    case 180: return CALL(180);                                      \
+    case 256: return CALL(256);                                      \
+    case 512: return CALL(512);                                      \
+    case 1024: return CALL(1024);                                    \
+    case 2048: return CALL(2048);                                    \
+    case 4096: return CALL(4096);                                    \
+    default: return BLINK_E_UNSUPPORTED;                             \
+  }
+
+}  // namespace
+
+extern "C" {
+
+const char* blink_status_string(blink_status s) {
+  switch (s) {
+    case BLINK_OK: return "ok";
+    case BLINK_E_ARG: return "invalid argument";
+    case BLINK_E_SIZE: return "invalid size";
+    case BLINK_E_UNSUPPORTED: return "unsupported configuration";
+    case BLINK_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case BLINK_E_HIP: return "HIP launch failed";
+    default: return "unknown status";
+  }
+}
+
+int32_t blink_supported_n(int32_t n) { return n_supported(n) ? 1 : 0; }
+
+size_t blink_workspace_size(const blink_problem* p, int32_t call) {
+  if (validate_problem(p, call) != BLINK_OK) return 0;
+  const long long n_img = (long long)p->n_time * p->n_chan;
+  return carve(p, call, default_chunk(p, call, n_img), nullptr, nullptr);
+}
+
+blink_status blink_grid(const blink_problem* p, const blink_inputs* in, blink_c32* grid,
+                        int32_t* counts, float* weight_sum, int32_t* n_dropped, void* workspace,
+                        size_t ws_bytes, blink_stream_t stream) {
+  blink_status e = validate_problem(p, BLINK_CALL_GRID);
+  if (e != BLINK_OK) return e;
+  if ((e = validate_inputs(p, in)) != BLINK_OK) return e;
+  const long long n_img = (long long)p->n_time * p->n_chan;
+  if (n_img > 0 && !grid) return BLINK_E_ARG;
+  if (n_img == 0) return BLINK_OK;
+  int chunk = 0;
+  if ((e = check_ws(p, BLINK_CALL_GRID, workspace, ws_bytes, &chunk)) != BLINK_OK) return e;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Work w{};
+  carve(p, BLINK_CALL_GRID, chunk, static_cast<char*>(workspace), &w);
+  run_sort(p, in, w, st);
+  ImgArgs a = make_args(p, in, w);
+  a.grid = reinterpret_cast<float2*>(grid);
+  a.counts = counts;
+  a.weight_sum = weight_sum;
+  a.n_dropped = n_dropped;
+#define BLINK_GRID_CALL(n) grid_n<n>(p, a, chunk, st)
+  BLINK_DISPATCH_N(p->grid_n, BLINK_GRID_CALL)
+#undef BLINK_GRID_CALL
+}
+
+blink_status blink_fft2d(const blink_c32* in, blink_c32* out, int32_t batch, int32_t n,
+                         int32_t sign, blink_stream_t stream) {
+  if (!in || !out) return BLINK_E_ARG;
+  if (sign != 1 && sign != -1) return BLINK_E_ARG;
+  if (batch < 0 || n < 1) return BLINK_E_SIZE;
+  if (!n_supported(n)) return BLINK_E_UNSUPPORTED;
+  if (batch == 0) return BLINK_OK;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const float2* i = reinterpret_cast<const float2*>(in);
+  float2* o = reinterpret_cast<float2*>(out);
+#define BLINK_FFT_CALL(N_) fft2d_n<N_>(i, o, batch, sign, st)
+  BLINK_DISPATCH_N(n, BLINK_FFT_CALL)
+#undef BLINK_FFT_CALL
+}
+
+blink_status blink_image_batch(const blink_problem* p, const blink_inputs* in, float* images,
+                               float* weight_sum, void* workspace, size_t ws_bytes,
+                               blink_stream_t stream) {
+  blink_status e = validate_problem(p, BLINK_CALL_IMAGE);
+  if (e != BLINK_OK) return e;
+  if ((e = validate_inputs(p, in)) != BLINK_OK) return e;
+  const long long n_img = (long long)p->n_time * p->n_chan;
+  if (n_img > 0 && !images) return BLINK_E_ARG;
+  if (n_img == 0) return BLINK_OK;
+  int chunk = 0;
+  if ((e = check_ws(p, BLINK_CALL_IMAGE, workspace, ws_bytes, &chunk)) != BLINK_OK) return e;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Work w{};
+  carve(p, BLINK_CALL_IMAGE, chunk, static_cast<char*>(workspace), &w);
+  run_sort(p, in, w, st);
+  ImgArgs a = make_args(p, in, w);
+  a.images = images;
+  a.weight_sum = weight_sum;
+#define BLINK_IMAGE_CALL(n) image_n<n>(p, a, chunk, st)
+  BLINK_DISPATCH_N(p->grid_n, BLINK_IMAGE_CALL)
+#undef BLINK_IMAGE_CALL
+}
+
+blink_status blink_degrid_adjoint(const blink_problem* p, const blink_inputs* in,
+                                  const float* image_grad, blink_c32* vis_grad,
+                                  blink_c32* gain_grad, void* workspace, size_t ws_bytes,
+                                  blink_stream_t stream) {
+  blink_status e = validate_problem(p, BLINK_CALL_ADJOINT);
+  if (e != BLINK_OK) return e;
+  if ((e = validate_inputs(p, in)) != BLINK_OK) return e;
+  const long long n_img = (long long)p->n_time * p->n_chan;
+  if (gain_grad && (!in->gains || !in->ant1 || !in->ant2 || p->n_ant < 1)) return BLINK_E_ARG;
+  if (n_img > 0 && p->n_bl > 0 && (!image_grad || !vis_grad)) return BLINK_E_ARG;
+  int chunk = 0;
+  if (n_img > 0 && p->n_bl > 0 &&
+      (e = check_ws(p, BLINK_CALL_ADJOINT, workspace, ws_bytes, &chunk)) != BLINK_OK)
+    return e;
+  if (n_img == 0 || p->n_bl == 0) {
+    if (gain_grad && p->n_ant > 0) {
+      hipLaunchKernelGGL(k_fill2, dim3(cdiv(p->n_ant, 256)), dim3(256), 0,
+                         reinterpret_cast<hipStream_t>(stream),
+                         reinterpret_cast<float2*>(gain_grad), (size_t)p->n_ant);
+      return launched();
+    }
+    return BLINK_OK;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Work w{};
+  carve(p, BLINK_CALL_ADJOINT, chunk, static_cast<char*>(workspace), &w);
+  run_sort(p, in, w, st);
+  ImgArgs a = make_args(p, in, w);
+  a.image_grad = image_grad;
+  a.vis_grad = reinterpret_cast<float2*>(vis_grad);
+  a.gain_grad = reinterpret_cast<float2*>(gain_grad);
+#define BLINK_ADJ_CALL(n) adjoint_n<n>(p, a, chunk, st)
+  BLINK_DISPATCH_N(p->grid_n, BLINK_ADJ_CALL)
+#undef BLINK_ADJ_CALL
+}
+
+}  // extern "C"

@@ -1,0 +1,228 @@
+// Device-side FFT building blocks for gfx950: small DFT codelets in registers
+// and a self-sorting (Stockham) mixed-radix transform of one length-N vector
+// held in LDS and processed by a single 64-lane wavefront.
+//
+// The 2D inverse transform of the dirty image (Sec. 4.3 Eq. 6, Sec. 5.2.2) is
+// evaluated as column transforms followed by row transforms built from these.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace blink {
+
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------- complex
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// a * (SIGN * i)
+template <int SIGN>
+__device__ __forceinline__ float2 mul_si(float2 a) {
+  return SIGN > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+// a * (c + SIGN * i * s)
+template <int SIGN>
+__device__ __forceinline__ float2 mul_cs(float2 a, float c, float s) {
+  const float ss = SIGN > 0 ? s : -s;
+  return make_float2(a.x * c - a.y * ss, a.x * ss + a.y * c);
+}
+
+// LDS index padding: one spare element every 16 keeps the strided accesses
+// of the Stockham stages off a single bank group.
+__device__ __forceinline__ constexpr int pad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int padded_len(int n) { return n + (n >> 4) + 4; }
+
+// Orders this wavefront's LDS reads before its later LDS writes (and vice
+// versa). LDS executes one wavefront's DS instructions in issue order, so a
+// compiler-level fence at wavefront scope is all that is needed.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------- codelets
+// X[k] = sum_n x[n] exp(SIGN 2 pi i n k / R), in place on v[0..R).
+namespace kc {
+constexpr float R2 = 0.70710678118654752440f;   // cos(pi/4)
+constexpr float C8 = 0.92387953251128675613f;   // cos(pi/8)
+constexpr float S8 = 0.38268343236508977173f;   // sin(pi/8)
+constexpr float S3 = 0.86602540378443864676f;   // sin(2 pi/3)
+constexpr float C51 = 0.30901699437494742410f;  // cos(2 pi/5)
+constexpr float S51 = 0.95105651629515357212f;  // sin(2 pi/5)
+constexpr float C52 = -0.80901699437494742410f; // cos(4 pi/5)
+constexpr float S52 = 0.58778525229247312917f;  // sin(4 pi/5)
+}  // namespace kc
+
+template <int SIGN>
+__device__ __forceinline__ void dft2(float2& a, float2& b) {
+  const float2 t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <int SIGN>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+  const float2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
+  const float2 s13 = cadd(a1, a3), d13 = mul_si<SIGN>(csub(a1, a3));
+  a0 = cadd(s02, s13);
+  a2 = csub(s02, s13);
+  a1 = cadd(d02, d13);
+  a3 = csub(d02, d13);
+}
+
+template <int SIGN>
+__device__ __forceinline__ void dft3(float2& a0, float2& a1, float2& a2) {
+  const float2 s = cadd(a1, a2);
+  const float2 d = mul_si<SIGN>(csub(a1, a2));
+  const float2 m = make_float2(a0.x - 0.5f * s.x, a0.y - 0.5f * s.y);
+  a0 = cadd(a0, s);
+  a1 = make_float2(m.x + kc::S3 * d.x, m.y + kc::S3 * d.y);
+  a2 = make_float2(m.x - kc::S3 * d.x, m.y - kc::S3 * d.y);
+}
+
+template <int SIGN>
+__device__ __forceinline__ void dft5(float2* a) {
+  const float2 s14 = cadd(a[1], a[4]), d14 = mul_si<SIGN>(csub(a[1], a[4]));
+  const float2 s23 = cadd(a[2], a[3]), d23 = mul_si<SIGN>(csub(a[2], a[3]));
+  const float2 x0 = a[0];
+  const float2 p1 = make_float2(x0.x + kc::C51 * s14.x + kc::C52 * s23.x, x0.y + kc::C51 * s14.y + kc::C52 * s23.y);
+  const float2 p2 = make_float2(x0.x + kc::C52 * s14.x + kc::C51 * s23.x, x0.y + kc::C52 * s14.y + kc::C51 * s23.y);
+  const float2 q1 = make_float2(kc::S51 * d14.x + kc::S52 * d23.x, kc::S51 * d14.y + kc::S52 * d23.y);
+  const float2 q2 = make_float2(kc::S52 * d14.x - kc::S51 * d23.x, kc::S52 * d14.y - kc::S51 * d23.y);
+  a[0] = make_float2(x0.x + s14.x + s23.x, x0.y + s14.y + s23.y);
+  a[1] = cadd(p1, q1);
+  a[4] = csub(p1, q1);
+  a[2] = cadd(p2, q2);
+  a[3] = csub(p2, q2);
+}
+
+// radix 8 as 4 x 2: x[2 n1 + n2] -> DFT4 over n1, twiddle w8^(n2 k1), DFT2 over n2
+template <int SIGN>
+__device__ __forceinline__ void dft8(float2* a) {
+  dft4<SIGN>(a[0], a[2], a[4], a[6]);
+  dft4<SIGN>(a[1], a[3], a[5], a[7]);
+  a[3] = mul_cs<SIGN>(a[3], kc::R2, kc::R2);
+  a[5] = mul_si<SIGN>(a[5]);
+  a[7] = mul_cs<SIGN>(a[7], -kc::R2, kc::R2);
+  float2 b[8];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    b[k1] = cadd(a[2 * k1], a[2 * k1 + 1]);
+    b[k1 + 4] = csub(a[2 * k1], a[2 * k1 + 1]);
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a[i] = b[i];
+}
+
+// radix 16 as 4 x 4: x[4 n1 + n2] -> DFT4 over n1, twiddle w16^(n2 k1), DFT4 over n2
+template <int SIGN>
+__device__ __forceinline__ void dft16(float2* a) {
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4<SIGN>(a[n2], a[n2 + 4], a[n2 + 8], a[n2 + 12]);
+  // a[n2 + 4 k1] now holds DFT4 output k1 of column n2; twiddle by w16^(n2 k1)
+  a[5] = mul_cs<SIGN>(a[5], kc::C8, kc::S8);      // n2=1 k1=1 : w^1
+  a[9] = mul_cs<SIGN>(a[9], kc::R2, kc::R2);      // n2=1 k1=2 : w^2
+  a[13] = mul_cs<SIGN>(a[13], kc::S8, kc::C8);    // n2=1 k1=3 : w^3
+  a[6] = mul_cs<SIGN>(a[6], kc::R2, kc::R2);      // n2=2 k1=1 : w^2
+  a[10] = mul_si<SIGN>(a[10]);                    // n2=2 k1=2 : w^4
+  a[14] = mul_cs<SIGN>(a[14], -kc::R2, kc::R2);   // n2=2 k1=3 : w^6
+  a[7] = mul_cs<SIGN>(a[7], kc::S8, kc::C8);      // n2=3 k1=1 : w^3
+  a[11] = mul_cs<SIGN>(a[11], -kc::R2, kc::R2);   // n2=3 k1=2 : w^6
+  a[15] = mul_cs<SIGN>(a[15], -kc::C8, -kc::S8);  // n2=3 k1=3 : w^9
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) dft4<SIGN>(a[4 * k1], a[4 * k1 + 1], a[4 * k1 + 2], a[4 * k1 + 3]);
+  // a[4 k1 + k2] holds X[k1 + 4 k2]: transpose into natural order
+  float2 b[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) b[k1 + 4 * k2] = a[4 * k1 + k2];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) a[i] = b[i];
+}
+
+template <int R, int SIGN>
+__device__ __forceinline__ void dft(float2* a) {
+  if constexpr (R == 2) dft2<SIGN>(a[0], a[1]);
+  else if constexpr (R == 3) dft3<SIGN>(a[0], a[1], a[2]);
+  else if constexpr (R == 4) dft4<SIGN>(a[0], a[1], a[2], a[3]);
+  else if constexpr (R == 5) dft5<SIGN>(a);
+  else if constexpr (R == 8) dft8<SIGN>(a);
+  else if constexpr (R == 16) dft16<SIGN>(a);
+  else static_assert(R == 2, "unsupported radix");
+}
+
+// ---------------------------------------------------------------- plans
+__host__ __device__ constexpr int pick_radix(int rem) {
+  return rem % 16 == 0 ? 16 : rem % 8 == 0 ? 8 : rem % 4 == 0 ? 4 : rem % 2 == 0 ? 2
+       : rem % 5 == 0 ? 5 : rem % 3 == 0 ? 3 : 0;
+}
+__host__ __device__ constexpr bool plan_ok(int n) {
+  if (n < 2) return false;
+  while (n > 1) {
+    const int r = pick_radix(n);
+    if (r == 0) return false;
+    n /= r;
+  }
+  return true;
+}
+
+// One Stockham stage of radix R after NS points have been combined:
+// butterfly j reads x[j + r N/R], twiddles by w_{NS R}^(SIGN (j mod NS) r),
+// applies the length-R DFT and writes y[(j / NS) NS R + (j mod NS) + r NS].
+// (Self-sorting radix-R formulation of the Stockham FFT; output in natural
+// order after the last stage.) In place on buf; one wavefront per vector.
+template <int N, int R, int NS, int SIGN>
+__device__ __forceinline__ void stockham_stage(float2* buf, int lane, const float2* __restrict__ tw) {
+  constexpr int NB = N / R;
+  constexpr int PER = (NB + WAVE - 1) / WAVE;
+  float2 v[PER][R];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int j = lane + p * WAVE;
+    if (NB % WAVE == 0 || j < NB) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[p][r] = buf[pad(j + r * NB)];
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int j = lane + p * WAVE;
+    if (NB % WAVE == 0 || j < NB) {
+      const int k = j % NS;
+      if constexpr (NS > 1) {
+        constexpr int STEP = N / (NS * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = tw[k * r * STEP];
+          if (SIGN < 0) w.y = -w.y;
+          v[p][r] = cmul(v[p][r], w);
+        }
+      }
+      dft<R, SIGN>(v[p]);
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[pad(base + r * NS)] = v[p][r];
+    }
+  }
+  wave_sync();
+}
+
+template <int N, int SIGN, int NS = 1>
+__device__ __forceinline__ void wave_fft(float2* buf, int lane, const float2* __restrict__ tw) {
+  if constexpr (NS < N) {
+    constexpr int R = pick_radix(N / NS);
+    static_assert(R != 0, "length not supported by the radix set");
+    stockham_stage<N, R, NS, SIGN>(buf, lane, tw);
+    wave_fft<N, SIGN, NS * R>(buf, lane, tw);
+  }
+}
+
+}  // namespace blink

@@ -1,0 +1,749 @@
+// HIP kernels of the dirty-imaging path for gfx950.
+//
+// Per timestep t (shared by all channels):
+//   k_sort_run / k_merge / k_sort_finish - order the usable baselines by u in
+//       metres (exact double comparison, ties by baseline index). Because
+//       rint(u * s_c) is non-decreasing in u for every s_c > 0, the baselines of
+//       one u cell form a contiguous run of this order at EVERY channel, so one
+//       sort serves all channels of the timestep.
+// Per chunk of images (t, c):
+//   k_bounds  - for every signed u cell, the first sorted position at or beyond
+//               it (a scan of the sorted u list at this channel's scale).
+//   k_grid_cols<N, MODE> - one wavefront per u cell column: gathers the column's
+//               baselines (directly and as conjugates of the mirror column),
+//               accumulates sums (and counts) in LDS, applies the weighting,
+//               then either writes the grid column (MODE_GRID) or runs the
+//               inverse transform along v and writes the rows of the cutout
+//               (MODE_IMAGE) - the grid never reaches HBM on the image path.
+//   k_rows<N> - two image rows per wavefront: Hermitian extension of the half
+//               spectrum (u cells 0..N/2-1), inverse transform along u, real
+//               part, FFT shift, 1/W and cutout fused into the store.
+// The adjoint (differentiation form) runs the same two passes transposed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "blink_fft.hpp"
+#include "twiddles.inc"
+
+namespace blink {
+
+constexpr double C_LIGHT = 299792458.0;   // m/s
+constexpr unsigned long long KEY_MAX = ~0ull;
+
+enum { MODE_IMAGE = 0, MODE_GRID = 1 };
+enum { VT_C64 = 0, VT_F16 = 1, VT_BF16 = 2 };
+
+// Cells per metre at frequency f: (f * (N dx)) / c, IEEE double, this order.
+__device__ __forceinline__ double cells_per_metre(double f, double ndx) {
+  const double p = f * ndx;
+  return p / C_LIGHT;
+}
+
+// Order-preserving map of a double to an unsigned 64-bit key.
+__device__ __forceinline__ unsigned long long order_key(double u) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(u);
+  return (b >> 63) ? ~b : (b | (1ull << 63));
+}
+
+// ============================================================== sort by u
+struct SortArgs {
+  int T, B;
+  int t0;                        // first timestep of this launch (grid.y covers t0 + blockIdx.y)
+  const double* uvw;             // [T][B][3]
+  const uint8_t* flags;          // [T][B] or null
+  unsigned long long* key[2];    // [T][B] ping-pong
+  int* idx[2];                   // [T][B]
+  int* n_unflagged;              // [T]
+  int* n_valid;                  // [T]
+  double* su;                    // [T][B] sorted u
+  double* sv;                    // [T][B] v in the same order
+  int* perm;                     // [T][B] baseline index in the same order
+};
+
+__global__ void k_sort_init(int* a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
+}
+
+// Bitonic sort of one run of RUN (key, index) pairs in LDS; the pair order is
+// total because indices are distinct, so the result equals a stable sort.
+template <int RUN>
+__global__ void __launch_bounds__(1024) k_sort_run(SortArgs a) {
+  __shared__ unsigned long long sk[RUN];
+  __shared__ int si[RUN];
+  __shared__ int s_unf;
+  const int t = a.t0 + blockIdx.y;
+  const int base = blockIdx.x * RUN;
+  const int len = min(RUN, a.B - base);
+  if (threadIdx.x == 0) s_unf = 0;
+  __syncthreads();
+  int unf = 0;
+  for (int i = threadIdx.x; i < RUN; i += blockDim.x) {
+    unsigned long long k = KEY_MAX;
+    int id = 0x7fffffff;
+    if (i < len) {
+      const int b = base + i;
+      const size_t o = (size_t)t * a.B + b;
+      const double u = a.uvw[o * 3 + 0];
+      const double v = a.uvw[o * 3 + 1];
+      const bool flagged = a.flags != nullptr && a.flags[o] != 0;
+      unf += flagged ? 0 : 1;
+      if (!flagged && isfinite(u) && isfinite(v)) k = order_key(u);
+      id = b;
+    }
+    sk[i] = k;
+    si[i] = id;
+  }
+  if (unf) atomicAdd(&s_unf, unf);
+  __syncthreads();
+  for (int k = 2; k <= RUN; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < RUN / 2; i += blockDim.x) {
+        const int lo = 2 * i - (i & (j - 1));
+        const int hi = lo + j;
+        const bool up = (lo & k) == 0;
+        const unsigned long long ka = sk[lo], kb = sk[hi];
+        const int ia = si[lo], ib = si[hi];
+        const bool gt = ka > kb || (ka == kb && ia > ib);
+        if (gt == up) {
+          sk[lo] = kb; sk[hi] = ka;
+          si[lo] = ib; si[hi] = ia;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < len; i += blockDim.x) {
+    const size_t o = (size_t)t * a.B + base + i;
+    a.key[0][o] = sk[i];
+    a.idx[0][o] = si[i];
+  }
+  if (threadIdx.x == 0 && s_unf) atomicAdd(&a.n_unflagged[t], s_unf);
+}
+
+// Merge neighbouring sorted runs of width w: each element's output position
+// is its rank in its own run plus the number of smaller elements in the other
+// run (binary search). All (key, index) pairs are distinct.
+__global__ void __launch_bounds__(256) k_merge(SortArgs a, int w, int src) {
+  const int t = a.t0 + blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.B) return;
+  const size_t tb = (size_t)t * a.B;
+  const unsigned long long* K = a.key[src] + tb;
+  const int* I = a.idx[src] + tb;
+  const int pb = (e / (2 * w)) * (2 * w);
+  const int lend = min(pb + w, a.B);
+  const int rend = min(pb + 2 * w, a.B);
+  const unsigned long long mk = K[e];
+  const int mi = I[e];
+  const bool left = e < lend;
+  int lo = left ? lend : pb, hi = left ? rend : lend;
+  const int own = left ? e - pb : e - lend;
+  while (lo < hi) {  // count of elements of the other run that are smaller
+    const int mid = (lo + hi) >> 1;
+    const unsigned long long km = K[mid];
+    const bool less = km < mk || (km == mk && I[mid] < mi);
+    if (less) lo = mid + 1; else hi = mid;
+  }
+  const int other = left ? lo - lend : lo - pb;
+  const int out = pb + own + other;
+  a.key[src ^ 1][tb + out] = mk;
+  a.idx[src ^ 1][tb + out] = mi;
+}
+
+__global__ void __launch_bounds__(256) k_sort_finish(SortArgs a, int src) {
+  const int t = a.t0 + blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.B) return;
+  const size_t tb = (size_t)t * a.B;
+  const unsigned long long k = a.key[src][tb + j];
+  const int b = a.idx[src][tb + j];
+  a.su[tb + j] = a.uvw[(tb + b) * 3 + 0];
+  a.sv[tb + j] = a.uvw[(tb + b) * 3 + 1];
+  a.perm[tb + j] = b;
+  const bool valid = k != KEY_MAX;
+  const bool next_invalid = (j + 1 == a.B) || a.key[src][tb + j + 1] == KEY_MAX;
+  if (valid && next_invalid) a.n_valid[t] = j + 1;
+}
+
+// ============================================================== cell bounds
+struct ImgArgs {
+  int T, C, B, N, M, weighting, norm, vis_type;
+  double ndx;                   // fl(N * dx)
+  const void* vis;              // [T][C][B] c64 or [T][C][B][2] f16/bf16
+  const float* vis_scale;       // [C]
+  const double* freq;           // [C]
+  const int* ant1;              // [B]
+  const int* ant2;              // [B]
+  const float2* gains;          // [A] or null
+  const double* su;             // [T][B]
+  const double* sv;             // [T][B]
+  const int* perm;              // [T][B]
+  const int* n_valid;           // [T]
+  const int* n_unflagged;       // [T]
+  int* bnd;                     // [chunk][N + 2]
+  int* wacc;                    // [chunk] weight-sum accumulators
+  int* kacc;                    // [chunk] kept-baseline accumulators
+  int img0, nimg;               // this chunk: images [img0, img0 + nimg)
+  float2* half;                 // [chunk][N/2][M] column-transformed half spectrum
+  float2* grid;                 // MODE_GRID: [T*C][N][N]
+  int* counts;                  // MODE_GRID: [T*C][N][N] or null
+  float* images;                // [T*C][M][M]
+  float* weight_sum;            // [T*C] or null
+  int* n_dropped;               // [T*C] or null
+  // adjoint
+  const float* image_grad;      // [T*C][M][M]
+  float2* gamma;                // [chunk][B] gradient w.r.t. V' per image
+  float2* vis_grad;             // [T][C][B]
+  float2* pacc;                 // [B] sum over images of gamma conj(V)
+  float2* gain_grad;            // [A]
+  int n_ant;
+};
+
+// bnd[c + N/2] = first sorted position j with clamp(rint(u_j s)) >= c for
+// c in [-N/2, N/2 + 1]; entry N + 1 is always n_valid. Also clears the
+// chunk's accumulators.
+__global__ void __launch_bounds__(256) k_bounds(ImgArgs a) {
+  const int li = blockIdx.x;
+  const int img = a.img0 + li;
+  const int t = img / a.C, ch = img - t * a.C;
+  const double s = cells_per_metre(a.freq[ch], a.ndx);
+  const int H = a.N / 2;
+  const int nv = a.n_valid[t];
+  const double* su = a.su + (size_t)t * a.B;
+  int* bnd = a.bnd + (size_t)li * (a.N + 2);
+  if (threadIdx.x == 0) { a.wacc[li] = 0; a.kacc[li] = 0; }
+  auto col = [&](int j) -> int {
+    const double x = rint(su[j] * s);
+    return (int)fmin(fmax(x, (double)-H), (double)H);
+  };
+  for (int j = threadIdx.x; j < nv; j += blockDim.x) {
+    const int cj = col(j);
+    const int cp = j == 0 ? -H - 1 : col(j - 1);
+    for (int c = cp + 1; c <= cj; ++c) bnd[c + H] = j;
+  }
+  const int clast = nv == 0 ? -H - 1 : col(nv - 1);
+  for (int c = clast + 1 + (int)threadIdx.x; c <= H + 1; c += blockDim.x) bnd[c + H] = nv;
+}
+
+// ============================================================== visibility load
+// g[a1] conj(g[a2]); an antenna index outside [0, n_ant) gives a zero gain.
+__device__ __forceinline__ float2 antenna_gain(const float2* g, int i, int n) {
+  return (unsigned)i < (unsigned)n ? g[i] : make_float2(0.f, 0.f);
+}
+template <class A>
+__device__ __forceinline__ float2 baseline_gain(const A& a, int b) {
+  const float2 g1 = antenna_gain(a.gains, a.ant1[b], a.n_ant);
+  const float2 g2 = antenna_gain(a.gains, a.ant2[b], a.n_ant);
+  return cmul(g1, cconj(g2));
+}
+__device__ __forceinline__ float2 load_vis(const ImgArgs& a, size_t off, int b, int ch) {
+  float2 v;
+  if (a.vis_type == VT_C64) {
+    v = static_cast<const float2*>(a.vis)[off];
+  } else if (a.vis_type == VT_F16) {
+    const __half2 h = static_cast<const __half2*>(a.vis)[off];
+    v = __half22float2(h);
+    const float sc = a.vis_scale[ch];
+    v.x *= sc; v.y *= sc;
+  } else {
+    const unsigned int w = static_cast<const unsigned int*>(a.vis)[off];
+    v.x = __uint_as_float(w << 16);
+    v.y = __uint_as_float(w & 0xffff0000u);
+    const float sc = a.vis_scale[ch];
+    v.x *= sc; v.y *= sc;
+  }
+  if (a.gains != nullptr) v = cmul(baseline_gain(a, b), v);
+  return v;
+}
+
+// Grid the points of sorted positions [lo, hi) into one column buffer:
+// value V' at row i_v (CONJ = false) or conj(V') at row -i_v (CONJ = true).
+// Only this wavefront touches the column, so the LDS adds happen in a fixed
+// order (chunks of the sorted list in sequence, lanes in LDS order).
+template <int N, bool CONJ, bool COUNT>
+__device__ __forceinline__ int grid_points(const ImgArgs& a, float2* buf, int* cnt, int lo, int hi,
+                                           int t, int ch, double s, int lane) {
+  const size_t tb = (size_t)t * a.B;
+  const size_t vb = ((size_t)t * a.C + ch) * a.B;
+  int kept = 0;
+  for (int j0 = lo; j0 < hi; j0 += WAVE) {
+    const int j = j0 + lane;
+    bool ok = j < hi;
+    int row = 0;
+    float2 val = make_float2(0.f, 0.f);
+    if (ok) {
+      const double iv = rint(a.sv[tb + j] * s);
+      ok = fabs(iv) < (double)(N / 2);
+      if (ok) {
+        const int b = a.perm[tb + j];
+        int r = (int)iv;
+        if (CONJ) r = -r;
+        row = r < 0 ? r + N : r;
+        val = load_vis(a, vb + b, b, ch);
+        if (CONJ) val.y = -val.y;
+      }
+    }
+    if (ok) {
+      float2* p = &buf[pad(row)];
+      atomicAdd(&p->x, val.x);
+      atomicAdd(&p->y, val.y);
+      if (COUNT) atomicAdd(&cnt[row], 1);
+    }
+    kept += __popcll(__ballot(ok));
+  }
+  return kept;
+}
+
+template <int N>
+struct Cols {
+  static constexpr int STRIDE = padded_len(N);                // complex per column buffer
+  static constexpr int CPW = N <= 1024 ? 8 : (N <= 2048 ? 4 : 2);  // columns (waves) per workgroup
+  static constexpr int THREADS = CPW * WAVE;
+  static size_t lds_bytes(bool counts) {
+    return (size_t)CPW * STRIDE * sizeof(float2) + (counts ? (size_t)CPW * N * sizeof(int) : 0);
+  }
+};
+
+// One workgroup = CPW consecutive u-cell columns of one image; one wavefront
+// per column. MODE_IMAGE: columns 0..N/2-1 (the half spectrum), transform
+// along v, rows of the cutout written to `half`. MODE_GRID: all N columns,
+// weighted grid and counts written out.
+template <int N, int MODE, bool UNI>
+__global__ void __launch_bounds__(Cols<N>::THREADS) k_grid_cols(ImgArgs a) {
+  extern __shared__ float4 lds_raw[];
+  constexpr int H = N / 2;
+  constexpr int CPW = Cols<N>::CPW;
+  float2* lds = reinterpret_cast<float2*>(lds_raw);
+  int* lcnt = reinterpret_cast<int*>(lds + CPW * Cols<N>::STRIDE);
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int li = blockIdx.y;
+  const int img = a.img0 + li;
+  const int t = img / a.C, ch = img - t * a.C;
+  const int col = blockIdx.x * CPW + wave;          // MODE_IMAGE: 0..H-1, MODE_GRID: 0..N-1
+  const int ncols = MODE == MODE_IMAGE ? H : N;
+  const bool active = col < ncols;
+  const int cs = MODE == MODE_IMAGE ? col : (col < H ? col : col - N);  // signed u cell
+  constexpr bool CNT = UNI || MODE == MODE_GRID;
+  float2* buf = lds + wave * Cols<N>::STRIDE;
+  int* cnt = CNT ? lcnt + wave * N : nullptr;
+  const double s = cells_per_metre(a.freq[ch], a.ndx);
+
+  for (int r = lane; r < Cols<N>::STRIDE; r += WAVE) buf[r] = make_float2(0.f, 0.f);
+  if (CNT)
+    for (int r = lane; r < N; r += WAVE) cnt[r] = 0;
+  wave_sync();
+
+  int kept_b = 0, wcontrib = 0;
+  if (active && cs != H && cs != -H) {
+    const int* bnd = a.bnd + (size_t)li * (N + 2);
+    const int dlo = bnd[cs + H], dhi = bnd[cs + 1 + H];
+    const int clo = bnd[-cs + H], chi = bnd[-cs + 1 + H];
+    const int kd = grid_points<N, false, CNT>(a, buf, cnt, dlo, dhi, t, ch, s, lane);
+    const int kc = grid_points<N, true, CNT>(a, buf, cnt, clo, chi, t, ch, s, lane);
+    wave_sync();
+    // baselines counted once: the direct entry of every cell column, plus the
+    // conjugate entries of columns whose mirror the image path never visits
+    kept_b = kd + ((MODE == MODE_IMAGE && cs > 0) ? kc : 0);
+    const int mult = (MODE == MODE_IMAGE && cs > 0) ? 2 : 1;
+    if (UNI) {
+      int occ = 0;
+      for (int r = lane; r < N; r += WAVE) {
+        const int n = cnt[r];
+        if (n > 0) {
+          float2 v = buf[pad(r)];
+          v.x = v.x / (float)n;
+          v.y = v.y / (float)n;
+          buf[pad(r)] = v;
+          ++occ;
+        }
+      }
+      for (int o = WAVE / 2; o > 0; o >>= 1) occ += __shfl_xor(occ, o);
+      wcontrib = mult * occ;
+      wave_sync();
+    } else {
+      wcontrib = mult * (kd + kc);
+    }
+    if (lane == 0) {
+      atomicAdd(&a.wacc[li], wcontrib);
+      atomicAdd(&a.kacc[li], kept_b);
+    }
+  }
+
+  if (MODE == MODE_IMAGE) {
+    if (active) {
+      wave_fft<N, +1>(buf, lane, TwTable<N>::get());
+      // rows of the cutout: output row m holds v-frequency q = (m - M/2) mod N
+      float2* dst = a.half + ((size_t)li * H + col) * a.M;
+      const int M = a.M;
+      for (int m = lane; m < M; m += WAVE) {
+        int q = m - M / 2;
+        q = q < 0 ? q + N : q;
+        dst[m] = buf[pad(q)];
+      }
+    }
+  } else {
+    __syncthreads();
+    // write the CPW-column tile row by row (CPW consecutive cells per row)
+    const int c0 = blockIdx.x * CPW;
+    float2* g = a.grid + (size_t)img * N * N;
+    int* gc = a.counts ? a.counts + (size_t)img * N * N : nullptr;
+    for (int e = threadIdx.x; e < N * CPW; e += blockDim.x) {
+      const int r = e / CPW, w = e % CPW;
+      if (c0 + w < N) {
+        g[(size_t)r * N + c0 + w] = lds[w * Cols<N>::STRIDE + pad(r)];
+        if (gc) gc[(size_t)r * N + c0 + w] = lcnt[w * N + r];
+      }
+    }
+  }
+}
+
+__global__ void k_grid_finish(ImgArgs a) {
+  const int li = blockIdx.x * blockDim.x + threadIdx.x;
+  if (li >= a.nimg) return;
+  const int img = a.img0 + li;
+  const int t = img / a.C;
+  if (a.weight_sum) a.weight_sum[img] = (float)a.wacc[li];
+  if (a.n_dropped) a.n_dropped[img] = a.n_unflagged[t] - a.kacc[li];
+}
+
+// ============================================================== row pass
+template <int N>
+struct Rows {
+  static constexpr int STRIDE = padded_len(N) + 4;   // +4 complex shifts buffers across banks
+  static constexpr int PPW = N <= 1024 ? 8 : (N <= 2048 ? 4 : 2);  // row pairs (waves) per WG
+  static constexpr int THREADS = PPW * WAVE;
+  static constexpr size_t LDS = (size_t)PPW * STRIDE * sizeof(float2);
+};
+
+// Inverse transform along u of two cutout rows per wavefront. The half
+// spectrum A[k] (k < N/2) of row m and B[k] of row m+1 are packed as
+// Z = A_full + i B_full with the Hermitian extensions A_full[N-k] = conj A[k]
+// (A_full[N/2] = 0: the Nyquist column is never gridded), so one complex
+// transform yields row m as Re z and row m+1 as Im z. The shift, 1/W and the
+// cutout are applied as the rows are stored.
+template <int N>
+__global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
+  extern __shared__ float4 lds_raw[];
+  constexpr int H = N / 2;
+  constexpr int PPW = Rows<N>::PPW;
+  constexpr int ST = Rows<N>::STRIDE;
+  float2* lds = reinterpret_cast<float2*>(lds_raw);
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int li = blockIdx.y;
+  const int img = a.img0 + li;
+  const int M = a.M;
+  const int npair = M / 2;
+  const int p0 = blockIdx.x * PPW;            // first row pair of this workgroup
+  const int W = a.wacc[li];
+  const float scale = a.norm ? (W > 0 ? 1.0f / (float)W : 0.0f) : 1.0f;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a.weight_sum) a.weight_sum[img] = (float)W;
+
+  const float4* src = reinterpret_cast<const float4*>(a.half + (size_t)li * H * M);
+  for (int e = threadIdx.x; e < H * PPW; e += blockDim.x) {
+    const int k = e / PPW, p = e % PPW;
+    if (p0 + p < npair) {
+      const float4 ab = src[((size_t)k * M + 2 * (p0 + p)) / 2];
+      float2* z = lds + p * ST;
+      if (k == 0) {
+        z[pad(0)] = make_float2(ab.x, ab.z);
+        z[pad(H)] = make_float2(0.f, 0.f);
+      } else {
+        z[pad(k)] = make_float2(ab.x - ab.w, ab.y + ab.z);
+        z[pad(N - k)] = make_float2(ab.x + ab.w, ab.z - ab.y);
+      }
+    }
+  }
+  __syncthreads();
+  const int pair = p0 + wave;
+  if (pair >= npair) return;
+  float2* z = lds + wave * ST;
+  wave_fft<N, +1>(z, lane, TwTable<N>::get());
+  float* r0 = a.images + ((size_t)img * M + 2 * pair) * M;
+  float* r1 = r0 + M;
+  for (int l = lane; l < M; l += WAVE) {
+    int q = l - M / 2;
+    q = q < 0 ? q + N : q;
+    const float2 v = z[pad(q)];
+    r0[l] = v.x * scale;
+    r1[l] = v.y * scale;
+  }
+}
+
+// ============================================================== plain 2D FFT
+template <int N>
+struct Fft2 {
+  static constexpr int STRIDE = padded_len(N) + 4;
+  static constexpr int VPW = N <= 1024 ? 8 : (N <= 2048 ? 4 : 2);   // vectors per workgroup
+  static constexpr int THREADS = VPW * WAVE;
+  static constexpr size_t LDS = (size_t)VPW * STRIDE * sizeof(float2);
+};
+
+template <int N, int SIGN>
+__global__ void __launch_bounds__(Fft2<N>::THREADS) k_fft_rows(const float2* in, float2* out, int nrows) {
+  extern __shared__ float4 lds_raw[];
+  float2* lds = reinterpret_cast<float2*>(lds_raw);
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const long row = (long)blockIdx.x * Fft2<N>::VPW + wave;
+  if (row >= nrows) return;
+  float2* z = lds + wave * Fft2<N>::STRIDE;
+  const float2* s = in + row * N;
+  for (int i = lane; i < N; i += WAVE) z[pad(i)] = s[i];
+  wave_sync();
+  wave_fft<N, SIGN>(z, lane, TwTable<N>::get());
+  float2* d = out + row * N;
+  for (int i = lane; i < N; i += WAVE) d[i] = z[pad(i)];
+}
+
+template <int N, int SIGN>
+__global__ void __launch_bounds__(Fft2<N>::THREADS) k_fft_cols(float2* data) {
+  extern __shared__ float4 lds_raw[];
+  constexpr int VPW = Fft2<N>::VPW;
+  float2* lds = reinterpret_cast<float2*>(lds_raw);
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int c0 = blockIdx.x * VPW;
+  float2* img = data + (size_t)blockIdx.y * N * N;
+  for (int e = threadIdx.x; e < N * VPW; e += blockDim.x) {
+    const int r = e / VPW, w = e % VPW;
+    if (c0 + w < N) lds[w * Fft2<N>::STRIDE + pad(r)] = img[(size_t)r * N + c0 + w];
+  }
+  __syncthreads();
+  if (c0 + wave < N) wave_fft<N, SIGN>(lds + wave * Fft2<N>::STRIDE, lane, TwTable<N>::get());
+  __syncthreads();
+  for (int e = threadIdx.x; e < N * VPW; e += blockDim.x) {
+    const int r = e / VPW, w = e % VPW;
+    if (c0 + w < N) img[(size_t)r * N + c0 + w] = lds[w * Fft2<N>::STRIDE + pad(r)];
+  }
+}
+
+// ============================================================== adjoint
+// Weight sums alone (the adjoint needs 1/W before anything else): counts of
+// kept entries (natural) or occupied cells (uniform) per half-spectrum column.
+template <int N, bool UNI>
+__global__ void __launch_bounds__(Cols<N>::THREADS) k_weights(ImgArgs a) {
+  extern __shared__ int lw_raw[];
+  constexpr int H = N / 2;
+  constexpr int CPW = Cols<N>::CPW;
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int li = blockIdx.y;
+  const int img = a.img0 + li;
+  const int t = img / a.C, ch = img - t * a.C;
+  const int cs = blockIdx.x * CPW + wave;
+  if (cs >= H) return;
+  int* cnt = lw_raw + wave * N;
+  const double s = cells_per_metre(a.freq[ch], a.ndx);
+  if (UNI) {
+    for (int r = lane; r < N; r += WAVE) cnt[r] = 0;
+    wave_sync();
+  }
+  const int* bnd = a.bnd + (size_t)li * (N + 2);
+  const size_t tb = (size_t)t * a.B;
+  int kept = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int c = pass == 0 ? cs : -cs;
+    const int lo = bnd[c + H], hi = bnd[c + 1 + H];
+    for (int j = lo + lane; j < hi; j += WAVE) {
+      const double iv = rint(a.sv[tb + j] * s);
+      if (fabs(iv) < (double)H) {
+        ++kept;
+        if (UNI) {
+          int r = (int)iv;
+          if (pass) r = -r;
+          atomicAdd(&cnt[r < 0 ? r + N : r], 1);
+        }
+      }
+    }
+  }
+  int w = kept;
+  if (UNI) {
+    wave_sync();
+    int occ = 0;
+    for (int r = lane; r < N; r += WAVE) occ += cnt[r] > 0;
+    w = occ;
+  }
+  for (int o = WAVE / 2; o > 0; o >>= 1) w += __shfl_xor(w, o);
+  if (lane == 0) atomicAdd(&a.wacc[li], (cs > 0 ? 2 : 1) * w);
+}
+
+// Adjoint of k_rows: image-gradient rows m, m+1 (zero outside the cutout,
+// times 1/W, shift undone) packed as z = a + i b, forward transform, then the
+// half-spectrum gradients c_k A[k], c_k B[k] (c_0 = 1, c_k = 2) with
+// A[k] = (Z[k] + conj Z[N-k]) / 2 and B[k] = (Z[k] - conj Z[N-k]) / (2i).
+template <int N>
+__global__ void __launch_bounds__(Rows<N>::THREADS) k_rows_adj(ImgArgs a) {
+  extern __shared__ float4 lds_raw[];
+  constexpr int H = N / 2;
+  constexpr int PPW = Rows<N>::PPW;
+  constexpr int ST = Rows<N>::STRIDE;
+  float2* lds = reinterpret_cast<float2*>(lds_raw);
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int li = blockIdx.y;
+  const int img = a.img0 + li;
+  const int M = a.M;
+  const int npair = M / 2;
+  const int p0 = blockIdx.x * PPW;
+  const int W = a.wacc[li];
+  const float scale = a.norm ? (W > 0 ? 1.0f / (float)W : 0.0f) : 1.0f;
+  const int pair = p0 + wave;
+  if (pair < npair) {
+    float2* z = lds + wave * ST;
+    for (int r = lane; r < ST; r += WAVE) z[r] = make_float2(0.f, 0.f);
+    wave_sync();
+    const float* g0 = a.image_grad + ((size_t)img * M + 2 * pair) * M;
+    const float* g1 = g0 + M;
+    for (int l = lane; l < M; l += WAVE) {
+      int q = l - M / 2;
+      q = q < 0 ? q + N : q;
+      z[pad(q)] = make_float2(g0[l] * scale, g1[l] * scale);
+    }
+    wave_sync();
+    wave_fft<N, -1>(z, lane, TwTable<N>::get());
+  }
+  __syncthreads();
+  float4* dst = reinterpret_cast<float4*>(a.half + (size_t)li * H * M);
+  for (int e = threadIdx.x; e < H * PPW; e += blockDim.x) {
+    const int k = e / PPW, p = e % PPW;
+    if (p0 + p < npair) {
+      const float2* z = lds + p * ST;
+      const float2 zk = z[pad(k)];
+      const float2 zm = z[pad(k == 0 ? 0 : N - k)];
+      float4 o;
+      if (k == 0) {
+        o = make_float4(zk.x, 0.f, zk.y, 0.f);
+      } else {  // 2 A[k] = Z[k] + conj Z[N-k]; 2 B[k] = -i (Z[k] - conj Z[N-k])
+        o = make_float4(zk.x + zm.x, zk.y - zm.y, zk.y + zm.y, -(zk.x - zm.x));
+      }
+      dst[((size_t)k * M + 2 * (p0 + p)) / 2] = o;
+    }
+  }
+}
+
+// Adjoint of k_grid_cols (MODE_IMAGE): column gradient at the cutout rows,
+// forward transform along v, cell weight, then gather (degrid) at every
+// entry of the column: gamma'_b += w G[i_v] (direct) or conj(w G[-i_v]).
+template <int N, bool UNI>
+__global__ void __launch_bounds__(Cols<N>::THREADS) k_cols_adj(ImgArgs a) {
+  extern __shared__ float4 lds_raw[];
+  constexpr int H = N / 2;
+  constexpr int CPW = Cols<N>::CPW;
+  float2* lds = reinterpret_cast<float2*>(lds_raw);
+  int* lcnt = reinterpret_cast<int*>(lds + CPW * Cols<N>::STRIDE);
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int li = blockIdx.y;
+  const int img = a.img0 + li;
+  const int t = img / a.C, ch = img - t * a.C;
+  const int cs = blockIdx.x * CPW + wave;
+  if (cs >= H) return;
+  float2* buf = lds + wave * Cols<N>::STRIDE;
+  int* cnt = UNI ? lcnt + wave * N : nullptr;
+  const double s = cells_per_metre(a.freq[ch], a.ndx);
+  const int M = a.M;
+  for (int r = lane; r < Cols<N>::STRIDE; r += WAVE) buf[r] = make_float2(0.f, 0.f);
+  if (UNI)
+    for (int r = lane; r < N; r += WAVE) cnt[r] = 0;
+  wave_sync();
+  const float2* srcc = a.half + ((size_t)li * H + cs) * M;
+  for (int m = lane; m < M; m += WAVE) {
+    int q = m - M / 2;
+    q = q < 0 ? q + N : q;
+    buf[pad(q)] = srcc[m];
+  }
+  const int* bnd = a.bnd + (size_t)li * (N + 2);
+  const int dlo = bnd[cs + H], dhi = bnd[cs + 1 + H];
+  const int clo = bnd[-cs + H], chi = bnd[-cs + 1 + H];
+  const size_t tb = (size_t)t * a.B;
+  if (UNI) {
+    for (int pass = 0; pass < 2; ++pass) {
+      const int lo = pass ? clo : dlo, hi = pass ? chi : dhi;
+      for (int j = lo + lane; j < hi; j += WAVE) {
+        const double iv = rint(a.sv[tb + j] * s);
+        if (fabs(iv) < (double)H) {
+          int r = (int)iv;
+          if (pass) r = -r;
+          atomicAdd(&cnt[r < 0 ? r + N : r], 1);
+        }
+      }
+    }
+  }
+  wave_sync();
+  wave_fft<N, -1>(buf, lane, TwTable<N>::get());
+  float2* gam = a.gamma + (size_t)li * a.B;
+  // direct entries (and, for column 0, the conjugate entry of the same baseline)
+  for (int pass = 0; pass < (cs == 0 ? 1 : 2); ++pass) {
+    const int lo = pass ? clo : dlo, hi = pass ? chi : dhi;
+    for (int j = lo + lane; j < hi; j += WAVE) {
+      const double iv = rint(a.sv[tb + j] * s);
+      if (fabs(iv) < (double)H) {
+        const int r = (int)iv;
+        const int rp = r < 0 ? r + N : r;
+        const int rm = -r < 0 ? -r + N : -r;
+        float2 g = make_float2(0.f, 0.f);
+        if (pass == 0) {
+          float2 v = buf[pad(rp)];
+          if (UNI) v = cscale(v, 1.0f / (float)cnt[rp]);
+          g = v;
+          if (cs == 0) {
+            float2 w = buf[pad(rm)];
+            if (UNI) w = cscale(w, 1.0f / (float)cnt[rm]);
+            g = cadd(g, cconj(w));
+          }
+        } else {
+          float2 w = buf[pad(rm)];
+          if (UNI) w = cscale(w, 1.0f / (float)cnt[rm]);
+          g = cconj(w);
+        }
+        gam[a.perm[tb + j]] = g;
+      }
+    }
+  }
+}
+
+__global__ void k_fill2(float2* p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = make_float2(0.f, 0.f);
+}
+
+// vis_grad = conj(g1) g2 gamma' and, per baseline, pacc += sum over this
+// chunk's images of gamma' conj(V) (images taken in order: deterministic).
+__global__ void __launch_bounds__(256) k_adj_finish(ImgArgs a) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.B) return;
+  float2 gb = make_float2(1.f, 0.f);
+  if (a.gains) gb = cconj(baseline_gain(a, b));
+  float2 acc = make_float2(0.f, 0.f);
+  for (int li = 0; li < a.nimg; ++li) {
+    const int img = a.img0 + li;
+    const float2 g = a.gamma[(size_t)li * a.B + b];
+    a.vis_grad[(size_t)img * a.B + b] = a.gains ? cmul(gb, g) : g;
+    if (a.gains) {
+      const float2 v = static_cast<const float2*>(a.vis)[(size_t)img * a.B + b];
+      acc = cadd(acc, cmul(g, cconj(v)));
+    }
+  }
+  if (a.gains) a.pacc[b] = cadd(a.pacc[b], acc);
+}
+
+// gain_grad[a] = sum_{b: a1 = a} g2 p_b + sum_{b: a2 = a} g1 conj(p_b)
+__global__ void __launch_bounds__(256) k_gain_grad(ImgArgs a) {
+  __shared__ float2 part[256];
+  const int ant = blockIdx.x;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
+    const int a1 = a.ant1[b], a2 = a.ant2[b];
+    const float2 p = a.pacc[b];
+    if (a1 == ant) acc = cadd(acc, cmul(antenna_gain(a.gains, a2, a.n_ant), p));
+    if (a2 == ant) acc = cadd(acc, cmul(antenna_gain(a.gains, a1, a.n_ant), cconj(p)));
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) part[threadIdx.x] = cadd(part[threadIdx.x], part[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.gain_grad[ant] = part[0];
+}
+
+}  // namespace blink

@@ -1,0 +1,156 @@
+"""CPU checks of the C ABI: the library loads, exports what include/blink.h
+declares, and rejects invalid arguments on the host with the documented
+status codes. Every call here fails validation before anything would be
+enqueued, so no GPU is touched."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2405_13478_amd as blink
+from paper_2405_13478_amd import blink as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+E_OK, E_ARG, E_SIZE, E_UNSUP, E_WS, E_HIP = 0, -1, -2, -3, -4, -5
+FAKE = ctypes.c_void_p(0x100000)   # never dereferenced: validation fails first
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return blink.load_library()
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "blink.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(blink_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    decl = _declared()
+    assert decl == sorted(B.EXPORTS)
+    for name in decl:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code in (E_OK, E_ARG, E_SIZE, E_UNSUP, E_WS, E_HIP):
+        assert lib.blink_status_string(code).decode()
+    assert lib.blink_status_string(E_OK).decode() == "ok"
+
+
+def test_supported_sizes(lib):
+    sup = [n for n in range(1, 5000) if lib.blink_supported_n(n)]
+    assert {128, 180, 1024, 2048}.issubset(sup)
+    assert all(n % 2 == 0 for n in sup)
+
+
+def _prob(**kw):
+    d = dict(n_time=2, n_chan=3, n_bl=10, n_ant=5, grid_n=64, out_n=32, pixscale=1e-2,
+             weighting=0, norm=1, vis_type=0, chunk_images=0)
+    d.update(kw)
+    return B.Problem(**d)
+
+
+def _inputs(**kw):
+    d = dict(vis=FAKE, vis_scale=None, uvw_m=FAKE, freq_hz=FAKE, flags=None, ant1=None,
+             ant2=None, gains=None)
+    d.update(kw)
+    return B.Inputs(**d)
+
+
+def _image(lib, p, inp, images=FAKE, ws=None, nbytes=0):
+    return lib.blink_image_batch(ctypes.byref(p) if p is not None else None,
+                                 ctypes.byref(inp) if inp is not None else None,
+                                 images, None, ws, nbytes, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(grid_n=63), E_SIZE), (dict(grid_n=0), E_SIZE), (dict(out_n=33), E_SIZE),
+    (dict(out_n=128), E_SIZE), (dict(out_n=0), E_SIZE), (dict(n_time=-1), E_SIZE),
+    (dict(grid_n=1000), E_UNSUP), (dict(grid_n=14, out_n=8), E_UNSUP),
+    (dict(pixscale=0.0), E_ARG), (dict(pixscale=float("nan")), E_ARG),
+    (dict(pixscale=float("inf")), E_ARG), (dict(pixscale=-1.0), E_ARG),
+    (dict(weighting=2), E_ARG), (dict(norm=5), E_ARG), (dict(vis_type=3), E_ARG),
+    (dict(chunk_images=-2), E_ARG),
+])
+def test_problem_validation(lib, kw, code):
+    assert _image(lib, _prob(**kw), _inputs()) == code
+    assert lib.blink_workspace_size(ctypes.byref(_prob(**kw)), 1) == 0
+
+
+def test_null_and_input_validation(lib):
+    assert _image(lib, None, _inputs()) == E_ARG
+    assert _image(lib, _prob(), None) == E_ARG
+    assert _image(lib, _prob(), _inputs(vis=None)) == E_ARG
+    assert _image(lib, _prob(), _inputs(uvw_m=None)) == E_ARG
+    assert _image(lib, _prob(), _inputs(freq_hz=None)) == E_ARG
+    assert _image(lib, _prob(), _inputs(), images=None) == E_ARG
+    # half-precision storage needs the per-channel scale
+    assert _image(lib, _prob(vis_type=1), _inputs()) == E_ARG
+    assert _image(lib, _prob(vis_type=2), _inputs()) == E_ARG
+    # gains need both antenna index arrays and n_ant >= 1
+    assert _image(lib, _prob(), _inputs(gains=FAKE)) == E_ARG
+    assert _image(lib, _prob(), _inputs(gains=FAKE, ant1=FAKE)) == E_ARG
+    assert _image(lib, _prob(n_ant=0), _inputs(gains=FAKE, ant1=FAKE, ant2=FAKE)) == E_ARG
+
+
+def test_workspace_validation(lib):
+    p = _prob()
+    need = lib.blink_workspace_size(ctypes.byref(p), 1)
+    assert need > 0
+    assert _image(lib, p, _inputs(), ws=None, nbytes=need) == E_WS
+    assert _image(lib, p, _inputs(), ws=FAKE, nbytes=need - 1) == E_WS
+    assert _image(lib, p, _inputs(), ws=ctypes.c_void_p(0x100010), nbytes=need) == E_WS
+
+
+def test_empty_problem_is_a_no_op(lib):
+    # zero images: nothing to do, no workspace needed, nothing enqueued
+    assert _image(lib, _prob(n_time=0), _inputs(vis=None, uvw_m=None, freq_hz=None)) == E_OK
+    assert _image(lib, _prob(n_chan=0), _inputs()) == E_OK
+
+
+def test_fft2d_validation(lib):
+    f = lib.blink_fft2d
+    assert f(None, FAKE, 1, 64, 1, None) == E_ARG
+    assert f(FAKE, None, 1, 64, 1, None) == E_ARG
+    assert f(FAKE, FAKE, 1, 64, 0, None) == E_ARG
+    assert f(FAKE, FAKE, 1, 64, 2, None) == E_ARG
+    assert f(FAKE, FAKE, -1, 64, 1, None) == E_SIZE
+    assert f(FAKE, FAKE, 1, 1000, 1, None) == E_UNSUP
+    assert f(FAKE, FAKE, 0, 64, 1, None) == E_OK
+
+
+def test_grid_and_adjoint_validation(lib):
+    p = _prob()
+    inp = _inputs()
+    g = lib.blink_grid
+    assert g(ctypes.byref(p), ctypes.byref(inp), None, None, None, None, None, 0, None) == E_ARG
+    assert g(ctypes.byref(_prob(grid_n=7)), ctypes.byref(inp), FAKE, None, None, None, None, 0,
+             None) == E_SIZE
+    a = lib.blink_degrid_adjoint
+    # the adjoint is built for complex64 visibilities only
+    assert a(ctypes.byref(_prob(vis_type=1)), ctypes.byref(_inputs(vis_scale=FAKE)), FAKE, FAKE,
+             None, None, 0, None) == E_UNSUP
+    # a gain gradient needs gains
+    assert a(ctypes.byref(p), ctypes.byref(inp), FAKE, FAKE, FAKE, None, 0, None) == E_ARG
+    assert a(ctypes.byref(p), ctypes.byref(inp), None, FAKE, None, None, 0, None) == E_ARG
+
+
+def test_workspace_sizes_scale(lib):
+    c3 = B.Problem(n_time=10, n_chan=768, n_bl=8128, n_ant=128, grid_n=1024, out_n=512,
+                   pixscale=8.3e-5, weighting=0, norm=1, vis_type=0, chunk_images=0)
+    s_grid = lib.blink_workspace_size(ctypes.byref(c3), 0)
+    s_img = lib.blink_workspace_size(ctypes.byref(c3), 1)
+    s_adj = lib.blink_workspace_size(ctypes.byref(c3), 2)
+    assert 0 < s_grid < s_img < s_adj
+    # an explicit chunk sets the half-spectrum share: chunk * N/2 * M * 8 bytes
+    c3.chunk_images = 4
+    s4 = lib.blink_workspace_size(ctypes.byref(c3), 1)
+    c3.chunk_images = 8
+    s8 = lib.blink_workspace_size(ctypes.byref(c3), 1)
+    assert s8 - s4 >= 4 * 512 * 512 * 8

@@ -1,0 +1,258 @@
+"""GPU parity of libblink.so against the FP64 oracle, through the C ABI.
+
+Bar: cell counts, weight sums and dropped counts bit-exact; images within
+1e-5 relative L2 per image (FP32 arithmetic against FP64). Inputs are the
+seeded synthetic workloads; the oracle runs on the very same bytes.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2405_13478_amd as blink
+from paper_2405_13478_amd import synth
+
+from _gpu_util import (REL_L2_FP32, device, inputs, oracle_images, per_image_rel_l2, rel_l2,
+                       run_image)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu] {request.node.name}", flush=True)
+    yield
+
+
+# ------------------------------------------------------------------ fft2d
+@pytest.mark.parametrize("n", [8, 12, 16, 32, 64, 128, 180, 256, 512, 1024, 2048])
+@pytest.mark.parametrize("sign", [1, -1])
+def test_fft2d_vs_oracle(n, sign):
+    rng = np.random.default_rng(n + (sign > 0))
+    batch = 2 if n <= 1024 else 1
+    x = (rng.normal(size=(batch, n, n)) + 1j * rng.normal(size=(batch, n, n))).astype(np.complex64)
+    xd = torch.from_numpy(x).to(device())
+    y = blink.fft2d(xd, sign).cpu().numpy()
+    for b in range(batch):
+        ref = oracle.fft2(x[b].astype(np.complex128), sign)
+        assert rel_l2(y[b].view(np.float32), ref.view(np.float64)) <= REL_L2_FP32
+
+
+def test_fft2d_in_place_and_sizes():
+    rng = np.random.default_rng(0)
+    x = (rng.normal(size=(3, 64, 64)) + 1j * rng.normal(size=(3, 64, 64))).astype(np.complex64)
+    xd = torch.from_numpy(x).to(device())
+    out = blink.fft2d(xd.clone(), +1)
+    blink.fft2d(xd, +1, out=xd)          # in == out
+    assert torch.equal(out, xd)
+
+
+# ------------------------------------------------------------------ grid
+def _grid_case(name):
+    if name == "plain128":
+        return synth.plain_single(), False
+    if name == "allsky180":
+        return synth.station_allsky(n_time=2, n_chan=3), False
+    if name == "wide1024":
+        return synth.widefield(n_time=1, n_chan=2, chan_stride=383), False
+    if name == "wide1024_gains":
+        return synth.widefield(n_time=1, n_chan=1, chan_stride=500), True
+    if name == "prec2048":
+        return synth.precision_station(n_time=1, n_chan=1), False
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["plain128", "allsky180", "wide1024", "wide1024_gains"])
+def test_grid_counts_bit_exact(name):
+    w, use_g = _grid_case(name)
+    d = inputs(w, with_gains=use_g)
+    g, c, wsum, drop = blink.grid(d["vis"], d["uvw_m"], d["freq_hz"], grid_n=w.grid_n,
+                                  pixscale=w.pixscale, weighting=w.weighting, flags=d["flags"],
+                                  gains=d.get("gains"), ant1=d.get("ant1"), ant2=d.get("ant2"))
+    torch.cuda.synchronize()
+    vis = d["vis"].cpu().numpy()
+    g, c, wsum, drop = g.cpu().numpy(), c.cpu().numpy(), wsum.cpu().numpy(), drop.cpu().numpy()
+    for i in range(w.n_img):
+        t, ch = divmod(i, w.n_chan)
+        s = oracle.uv_scale(w.freq_hz[ch], w.grid_n, w.pixscale)
+        fl = None if w.flags is None else w.flags[t]
+        iu, iv, keep = oracle.cell_index(w.uvw_m[t, :, 0], w.uvw_m[t, :, 1], s, w.grid_n, fl)
+        vp = oracle.apply_gains(vis[t, ch], w.gains if use_g else None, w.ant1, w.ant2)
+        S, cnt = oracle.grid(vp, iu, iv, keep, w.grid_n)
+        G, W = oracle.weight(S, cnt, w.weighting)
+        assert np.array_equal(c[i], cnt), f"counts differ in image {i}"
+        assert wsum[i] == W
+        n_unf = w.n_bl if fl is None else int((fl == 0).sum())
+        assert drop[i] == n_unf - int(keep.sum())
+        assert rel_l2(g[i].view(np.float32), G.view(np.float64)) <= 1e-6
+
+
+# ------------------------------------------------------------------ images
+@pytest.mark.parametrize("name", ["plain128", "allsky180", "wide1024", "wide1024_gains", "prec2048"])
+def test_image_parity(name):
+    w, use_g = _grid_case(name)
+    d = inputs(w, with_gains=use_g)
+    img, wsum = run_image(w, d)
+    ref, W = oracle_images(w, d["vis"].cpu().numpy(), range(w.n_img),
+                           gains=w.gains if use_g else None)
+    errs = per_image_rel_l2(img.cpu().numpy(), ref)
+    print(f"  max rel-L2 = {max(errs):.3e} over {len(errs)} images", flush=True)
+    assert max(errs) <= REL_L2_FP32
+    assert np.array_equal(wsum.cpu().numpy(), W.astype(np.float32))
+
+
+@pytest.mark.parametrize("norm", [0, 1])
+@pytest.mark.parametrize("out_n", [128, 64])
+def test_image_norm_and_cutout(norm, out_n):
+    w = synth.plain_single()
+    d = inputs(w)
+    img = blink.image_batch(d["vis"], d["uvw_m"], d["freq_hz"], grid_n=128, pixscale=w.pixscale,
+                            out_n=out_n, weighting=0, norm=norm)
+    ref, _ = oracle_images(w, d["vis"].cpu().numpy(), [0], norm=norm, out_n=out_n)
+    assert rel_l2(img.cpu().numpy()[0], ref[0]) <= REL_L2_FP32
+
+
+def test_point_source_at_phase_centre_gives_centred_peak():
+    w = synth.plain_single()
+    d = inputs(w)
+    vis = torch.full_like(d["vis"], 3.0 + 0j)
+    img = blink.image_batch(vis, d["uvw_m"], d["freq_hz"], grid_n=128, pixscale=w.pixscale,
+                            out_n=128, weighting=0, norm=1).cpu().numpy()[0]
+    assert np.unravel_index(np.argmax(img), img.shape) == (64, 64)
+    assert abs(img[64, 64] - 3.0) <= 3e-6 * 3.0
+
+
+# ------------------------------------------------------------------ determinism / batching
+def test_bitwise_repeatable_and_chunk_invariant():
+    w = synth.station_allsky(n_time=3, n_chan=4)
+    d = inputs(w)
+    a, _ = run_image(w, d)
+    b, _ = run_image(w, d)
+    c, _ = run_image(w, d, chunk_images=1)
+    e, _ = run_image(w, d, chunk_images=5)
+    assert torch.equal(a, b) and torch.equal(a, c) and torch.equal(a, e)
+
+
+def test_ragged_batch_equals_per_image_calls():
+    w = synth.station_allsky(n_time=3, n_chan=2)
+    d = inputs(w)
+    full, _ = run_image(w, d)
+    for t in range(w.n_time):
+        for ch in range(w.n_chan):
+            one = blink.image_batch(d["vis"][t:t + 1, ch:ch + 1].contiguous(),
+                                    d["uvw_m"][t:t + 1].contiguous(), d["freq_hz"][ch:ch + 1].contiguous(),
+                                    grid_n=w.grid_n, pixscale=w.pixscale, out_n=w.out_n,
+                                    weighting=w.weighting, norm=w.norm,
+                                    flags=d["flags"][t:t + 1].contiguous())
+            assert torch.equal(one[0], full[t * w.n_chan + ch])
+
+
+# ------------------------------------------------------------------ precision form
+@pytest.mark.parametrize("dt", [torch.float16, torch.bfloat16])
+def test_half_storage_parity(dt):
+    w = synth.precision_station(n_time=1, n_chan=2)
+    w.grid_n = w.out_n = 512          # keep the oracle fast; same layout and weighting
+    w.pixscale = synth.oversampled_pixscale(10000.0, float(w.freq_hz.max()))
+    d = inputs(w)
+    q, sig = synth.quantize_vis(d["vis"], dt)
+    d16 = dict(d, vis=q, vis_scale=sig)
+    img, _ = run_image(w, d16)
+    qn = q.cpu()
+    if dt == torch.bfloat16:
+        bits = qn.view(torch.int16).numpy().view(np.uint16)
+        re, im = bits[..., 0], bits[..., 1]
+    else:
+        re, im = qn[..., 0].numpy(), qn[..., 1].numpy()
+    deq = oracle.dequantize(re, im, sig.cpu().numpy()[None, :, None].astype(np.float64))
+    ref, _ = oracle_images(w, deq, range(w.n_img))
+    errs = per_image_rel_l2(img.cpu().numpy(), ref)
+    assert max(errs) <= REL_L2_FP32
+    # error of the storage format itself, against the unquantised FP64 oracle
+    ref64, _ = oracle_images(w, d["vis"].cpu().numpy(), range(w.n_img))
+    e64 = per_image_rel_l2(img.cpu().numpy(), ref64)
+    print(f"  {dt}: rel-L2 vs dequantised oracle {max(errs):.2e}, vs FP64 unquantised {max(e64):.2e}")
+    assert max(e64) <= (5e-3 if dt == torch.float16 else 3e-2)
+
+
+# ------------------------------------------------------------------ edge cases
+def _tiny(n=16, nb=40, seed=0, flags=None, uv=None):
+    rng = np.random.default_rng(seed)
+    w = synth.plain_single()
+    w.grid_n = w.out_n = n
+    w.pixscale = 1.0 / n
+    w.freq_hz = np.array([synth.C_LIGHT])          # s = 1 cell per metre exactly
+    w.ant1 = np.arange(nb, dtype=np.int32) % 7
+    w.ant2 = (w.ant1 + 1).astype(np.int32)
+    if uv is None:
+        uv = rng.uniform(-n / 2 - 2, n / 2 + 2, size=(nb, 2))
+    w.uvw_m = np.zeros((1, nb, 3))
+    w.uvw_m[0, :, :2] = uv
+    w.flags = flags
+    vis = (rng.normal(size=(1, 1, nb)) + 1j * rng.normal(size=(1, 1, nb))).astype(np.complex64)
+    return w, vis
+
+
+def _run_tiny(w, vis, weighting=0):
+    w.weighting = weighting
+    dev = device()
+    d = dict(vis=torch.from_numpy(vis).to(dev), uvw_m=torch.from_numpy(w.uvw_m).to(dev),
+             freq_hz=torch.from_numpy(w.freq_hz).to(dev),
+             flags=None if w.flags is None else torch.from_numpy(w.flags).to(dev))
+    img, wsum = run_image(w, d)
+    g, c, gw, drop = blink.grid(d["vis"], d["uvw_m"], d["freq_hz"], grid_n=w.grid_n,
+                                pixscale=w.pixscale, weighting=weighting, flags=d["flags"])
+    torch.cuda.synchronize()
+    return img.cpu().numpy(), wsum.cpu().numpy(), c.cpu().numpy(), drop.cpu().numpy()
+
+
+@pytest.mark.parametrize("weighting", [0, 1])
+def test_ties_edges_and_out_of_grid(weighting):
+    # half-integer coordinates (ties), the +-N/2 edge and baselines off the grid
+    n = 16
+    base = np.array([0.5, 1.5, 2.5, -0.5, -1.5, 7.49, 7.5, -7.5, 8.5, -7.49, 0.0, 3.0])
+    uv = np.stack(np.meshgrid(base, base), -1).reshape(-1, 2)
+    w, vis = _tiny(n=n, nb=len(uv), uv=uv, seed=3)
+    img, wsum, cnt, drop = _run_tiny(w, vis, weighting)
+    r = oracle.image_one(vis[0, 0], uv[:, 0], uv[:, 1], w.freq_hz[0], n, w.pixscale, n,
+                         weighting, 1)
+    assert np.array_equal(cnt[0], r["counts"])
+    assert drop[0] == len(uv) - r["keep"].sum()
+    assert wsum[0] == r["W"]
+    assert rel_l2(img[0], r["image"]) <= REL_L2_FP32
+
+
+def test_all_flagged_and_non_finite_coordinates():
+    n = 16
+    w, vis = _tiny(n=n, nb=30, seed=4)
+    w.uvw_m[0, 3, 0] = np.nan
+    w.uvw_m[0, 5, 1] = np.inf
+    w.uvw_m[0, 7, 0] = -np.inf
+    img, wsum, cnt, drop = _run_tiny(w, vis)
+    r = oracle.image_one(vis[0, 0], w.uvw_m[0, :, 0], w.uvw_m[0, :, 1], w.freq_hz[0], n,
+                         w.pixscale, n, 0, 1)
+    assert np.array_equal(cnt[0], r["counts"]) and drop[0] == 30 - r["keep"].sum()
+    assert rel_l2(img[0], r["image"]) <= REL_L2_FP32
+    w.flags = np.ones((1, 30), np.uint8)
+    img, wsum, cnt, drop = _run_tiny(w, vis)
+    assert wsum[0] == 0 and cnt[0].sum() == 0 and drop[0] == 0
+    assert np.all(img[0] == 0)
+
+
+def test_zero_baselines_gives_zero_images():
+    w, vis = _tiny(n=16, nb=1, seed=5)
+    dev = device()
+    vis0 = torch.zeros((2, 1, 0), dtype=torch.complex64, device=dev)
+    img = blink.image_batch(vis0, torch.zeros((2, 0, 3), dtype=torch.float64, device=dev),
+                            torch.from_numpy(w.freq_hz).to(dev), grid_n=16, pixscale=w.pixscale)
+    torch.cuda.synchronize()
+    assert img.shape == (2, 16, 16) and torch.count_nonzero(img) == 0
+
+
+def test_origin_baseline_lands_in_column_zero():
+    # i_u = 0 baselines contribute both directly and as conjugates to column 0
+    uv = np.array([[0.0, 3.0], [0.2, -2.0], [0.0, 0.0], [4.0, 0.0]])
+    w, vis = _tiny(n=8, nb=4, uv=uv, seed=6)
+    img, wsum, cnt, drop = _run_tiny(w, vis)
+    r = oracle.image_one(vis[0, 0], uv[:, 0], uv[:, 1], w.freq_hz[0], 8, w.pixscale, 8, 0, 1)
+    assert np.array_equal(cnt[0], r["counts"])
+    assert rel_l2(img[0], r["image"]) <= REL_L2_FP32
