@@ -12,7 +12,9 @@
  * --------------------------------
  * - blink_problem and blink_inputs are host structs, read during the call
  *   only. Every array they (or the calls) point to is DEVICE memory, owned by
- *   the caller; the library never allocates, frees or synchronises.
+ *   the caller; the library never allocates device memory, frees or
+ *   synchronises (the one exception, blink_image_batch_timed, is an
+ *   instrumentation call that waits for its own timing events).
  * - Scratch memory comes from a caller-provided device workspace of at least
  *   blink_workspace_size() bytes, 256-byte aligned. Its contents on entry are
  *   irrelevant; it must not be shared by calls that may run concurrently.
@@ -166,6 +168,30 @@ blink_status blink_degrid_adjoint(const blink_problem* p, const blink_inputs* in
                                   const float* image_grad, blink_c32* vis_grad,
                                   blink_c32* gain_grad, void* workspace,
                                   size_t ws_bytes, blink_stream_t stream);
+
+/*
+ * Per-kernel timing of the image path (instrumentation for benchmarks and
+ * profiling; not for graph capture). Kernel classes of blink_image_batch:
+ *   0 = per-timestep sort (all its launches), 1 = cell bounds,
+ *   2 = gridding + column inverse transform, 3 = row inverse transform with
+ *   the fused shift / 1/W / cutout.
+ */
+#define BLINK_KCLASS_COUNT 4
+typedef struct {
+  double  ms[BLINK_KCLASS_COUNT];        /* summed kernel time, milliseconds   */
+  int64_t launches[BLINK_KCLASS_COUNT];  /* number of launches of the class    */
+} blink_kernel_times;
+
+/*
+ * Same work and results as blink_image_batch, with a HIP event recorded on
+ * `stream` before and after every launch. Blocks the host until the last
+ * event completes, then writes the per-class sums into *times (which must be
+ * non-null). Results are bitwise identical to blink_image_batch.
+ */
+blink_status blink_image_batch_timed(const blink_problem* p, const blink_inputs* in,
+                                     float* images, float* weight_sum, void* workspace,
+                                     size_t ws_bytes, blink_stream_t stream,
+                                     blink_kernel_times* times);
 
 #ifdef __cplusplus
 }

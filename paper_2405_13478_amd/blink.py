@@ -24,7 +24,10 @@ STATUS = {0: "BLINK_OK", -1: "BLINK_E_ARG", -2: "BLINK_E_SIZE", -3: "BLINK_E_UNS
 
 # every symbol include/blink.h declares
 EXPORTS = ("blink_status_string", "blink_supported_n", "blink_workspace_size", "blink_grid",
-           "blink_fft2d", "blink_image_batch", "blink_degrid_adjoint")
+           "blink_fft2d", "blink_image_batch", "blink_degrid_adjoint", "blink_image_batch_timed")
+
+# kernel classes reported by blink_image_batch_timed
+KCLASS = ("sort", "bounds", "grid_cols", "rows")
 
 
 class BlinkError(RuntimeError):
@@ -45,6 +48,10 @@ class Inputs(ctypes.Structure):
     _fields_ = [("vis", ctypes.c_void_p), ("vis_scale", ctypes.c_void_p), ("uvw_m", ctypes.c_void_p),
                 ("freq_hz", ctypes.c_void_p), ("flags", ctypes.c_void_p), ("ant1", ctypes.c_void_p),
                 ("ant2", ctypes.c_void_p), ("gains", ctypes.c_void_p)]
+
+
+class KernelTimes(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 4), ("launches", ctypes.c_int64 * 4)]
 
 
 _lib = None
@@ -75,6 +82,8 @@ def load_library(path: str | None = None):
     lib.blink_image_batch.restype = i32
     lib.blink_degrid_adjoint.argtypes = [P, I, vp, vp, vp, vp, sz, vp]
     lib.blink_degrid_adjoint.restype = i32
+    lib.blink_image_batch_timed.argtypes = [P, I, vp, vp, vp, sz, vp, ctypes.POINTER(KernelTimes)]
+    lib.blink_image_batch_timed.restype = i32
     if path is None:
         _lib = lib
     return lib
@@ -165,8 +174,12 @@ def workspace(p: Problem, call: int, device) -> torch.Tensor:
 # ---------------------------------------------------------------- calls
 def image_batch(vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None, weighting=NATURAL,
                 norm=NORM_WEIGHTS, flags=None, vis_scale=None, ant1=None, ant2=None, gains=None,
-                chunk_images=0, images=None, weight_sum=None, ws=None, stream=None):
-    """Dirty images [T*C][M][M] float32 of the cube (blink_image_batch)."""
+                chunk_images=0, images=None, weight_sum=None, ws=None, stream=None, times=None):
+    """Dirty images [T*C][M][M] float32 of the cube (blink_image_batch).
+
+    With ``times`` (a KernelTimes) the instrumented twin blink_image_batch_timed
+    runs instead: same results, per-kernel-class event timings, host waits.
+    """
     lib = load_library()
     p = make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, weighting, norm, gains, chunk_images)
     inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains)
@@ -177,9 +190,12 @@ def image_batch(vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None, weighting=
     _dev(weight_sum, "weight_sum", torch.float32, (n_img,))
     if ws is None:
         ws = workspace(p, CALL_IMAGE, vis.device)
-    code = lib.blink_image_batch(ctypes.byref(p), ctypes.byref(inp), _ptr(images), _ptr(weight_sum),
-                                 _ptr(ws) if ws.numel() else None, ws.numel(), _stream(stream))
-    _check(code, "blink_image_batch")
+    args = (ctypes.byref(p), ctypes.byref(inp), _ptr(images), _ptr(weight_sum),
+            _ptr(ws) if ws.numel() else None, ws.numel(), _stream(stream))
+    if times is None:
+        _check(lib.blink_image_batch(*args), "blink_image_batch")
+    else:
+        _check(lib.blink_image_batch_timed(*args, ctypes.byref(times)), "blink_image_batch_timed")
     return images
 
 

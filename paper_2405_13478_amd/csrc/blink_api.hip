@@ -7,6 +7,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <utility>
+#include <vector>
 
 #include "blink.h"
 #include "blink_kernels.hpp"
@@ -18,7 +20,7 @@ namespace {
 constexpr int SORT_RUN_SMALL = 1024;
 constexpr int SORT_RUN = 8192;
 constexpr int MAX_GRID_Y = 65535;
-constexpr size_t CHUNK_TARGET_BYTES = size_t(96) << 20;   // half-spectrum bytes per chunk
+constexpr size_t CHUNK_TARGET_BYTES = size_t(1) << 30;    // half-spectrum bytes per chunk
 
 bool n_supported(int n) {
   switch (n) {
@@ -40,8 +42,9 @@ struct Work {
   double* sv;
   int* perm;
   int* bnd;
-  int* wacc;
-  int* kacc;
+  int* wpart;
+  int* kpart;
+  int wstride;
   float2* half;
   float2* gamma;
   float2* pacc;
@@ -75,9 +78,11 @@ size_t carve(const blink_problem* p, int call, int chunk, char* base, Work* w) {
   x.su = (double*)take(T * B * 8);
   x.sv = (double*)take(T * B * 8);
   x.perm = (int*)take(T * B * 4);
-  x.bnd = (int*)take((size_t)chunk * (N + 2) * 4);
-  x.wacc = (int*)take((size_t)chunk * 4);
-  x.kacc = (int*)take((size_t)chunk * 4);
+  const size_t n_img = (size_t)p->n_time * (size_t)p->n_chan;
+  x.bnd = (int*)take(n_img * (N + 2) * 4);
+  x.wstride = (int)((N + cols_per_wg((int)N) - 1) / cols_per_wg((int)N));
+  x.wpart = (int*)take(n_img * x.wstride * 4);
+  x.kpart = (int*)take(n_img * x.wstride * 4);
   if (call == BLINK_CALL_IMAGE || call == BLINK_CALL_ADJOINT)
     x.half = (float2*)take((size_t)chunk * (N / 2) * M * 8);
   if (call == BLINK_CALL_ADJOINT) {
@@ -134,10 +139,57 @@ blink_status launched() {
 
 inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
+// Records a start/end HIP event pair around launches when active (timed
+// entry point); a no-op otherwise.
+struct Timer {
+  hipStream_t st = nullptr;
+  bool on = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
+  int cls = -1;
+  hipEvent_t cur = nullptr;
+  void begin(int c) {
+    if (!on) return;
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+    hipEventRecord(e, st);
+    cls = c;
+    cur = e;
+  }
+  void end() {
+    if (!on || !cur) return;
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+    hipEventRecord(e, st);
+    ev.push_back({cls, {cur, e}});
+    cur = nullptr;
+  }
+  blink_status collect(blink_kernel_times* out) {
+    for (int k = 0; k < BLINK_KCLASS_COUNT; ++k) { out->ms[k] = 0.0; out->launches[k] = 0; }
+    blink_status r = BLINK_OK;
+    if (!ev.empty() && hipEventSynchronize(ev.back().second.second) != hipSuccess) r = BLINK_E_HIP;
+    for (auto& x : ev) {
+      float ms = 0.f;
+      if (r == BLINK_OK && hipEventElapsedTime(&ms, x.second.first, x.second.second) == hipSuccess) {
+        out->ms[x.first] += ms;
+        out->launches[x.first] += 1;
+      }
+      hipEventDestroy(x.second.first);
+      hipEventDestroy(x.second.second);
+    }
+    ev.clear();
+    return r;
+  }
+};
+
 // per-timestep order of the usable baselines by u (metres)
-void run_sort(const blink_problem* p, const blink_inputs* in, const Work& w, hipStream_t st) {
+void run_sort(const blink_problem* p, const blink_inputs* in, const Work& w, hipStream_t st,
+              Timer* tm = nullptr) {
+  Timer none;
+  Timer& T_ = tm ? *tm : none;
   const int T = p->n_time, B = p->n_bl;
+  T_.begin(0);
   hipLaunchKernelGGL(k_sort_init, dim3(cdiv(2LL * T, 256)), dim3(256), 0, st, w.counters, 2 * T);
+  T_.end();
   if (B == 0 || T == 0) return;
   SortArgs s{};
   s.T = T; s.B = B;
@@ -150,16 +202,22 @@ void run_sort(const blink_problem* p, const blink_inputs* in, const Work& w, hip
   for (int t0 = 0; t0 < T; t0 += MAX_GRID_Y) {
     const int nt = std::min(MAX_GRID_Y, T - t0);
     s.t0 = t0;
+    T_.begin(0);
     if (run == SORT_RUN_SMALL)
       hipLaunchKernelGGL((k_sort_run<SORT_RUN_SMALL>), dim3(1, nt), dim3(1024), 0, st, s);
     else
       hipLaunchKernelGGL((k_sort_run<SORT_RUN>), dim3(cdiv(B, SORT_RUN), nt), dim3(1024), 0, st, s);
+    T_.end();
     int src = 0;
     for (long long wdt = run; wdt < B; wdt *= 2) {
+      T_.begin(0);
       hipLaunchKernelGGL(k_merge, dim3(cdiv(B, 256), nt), dim3(256), 0, st, s, (int)wdt, src);
+      T_.end();
       src ^= 1;
     }
+    T_.begin(0);
     hipLaunchKernelGGL(k_sort_finish, dim3(cdiv(B, 256), nt), dim3(256), 0, st, s, src);
+    T_.end();
   }
 }
 
@@ -174,27 +232,35 @@ ImgArgs make_args(const blink_problem* p, const blink_inputs* in, const Work& w)
   a.n_ant = p->n_ant;
   a.su = w.su; a.sv = w.sv; a.perm = w.perm;
   a.n_unflagged = w.counters; a.n_valid = w.counters + p->n_time;
-  a.bnd = w.bnd; a.wacc = w.wacc; a.kacc = w.kacc;
+  a.bnd = w.bnd; a.wpart = w.wpart; a.kpart = w.kpart; a.wstride = w.wstride;
   a.half = w.half; a.gamma = w.gamma; a.pacc = w.pacc;
   return a;
 }
 
 template <int N>
-blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t st) {
+blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t st, Timer* tm) {
+  Timer& T_ = *tm;
   const long long n_img = (long long)p->n_time * p->n_chan;
   const bool uni = p->weighting == BLINK_UNIFORM;
   const size_t lds1 = Cols<N>::lds_bytes(uni);
+  a.wtiles = (int)cdiv(N / 2, Cols<N>::CPW);
+  T_.begin(1);
+  hipLaunchKernelGGL(k_bounds, dim3((unsigned)n_img), dim3(256), 0, st, a);
+  T_.end();
   for (long long i0 = 0; i0 < n_img; i0 += chunk) {
     const int n = (int)std::min<long long>(chunk, n_img - i0);
     a.img0 = (int)i0; a.nimg = n;
-    hipLaunchKernelGGL(k_bounds, dim3(n), dim3(256), 0, st, a);
     const dim3 g1(cdiv(N / 2, Cols<N>::CPW), n);
+    T_.begin(2);
     if (uni)
       hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, true>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
     else
       hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, false>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
+    T_.end();
     const dim3 g2(cdiv(p->out_n / 2, Rows<N>::PPW), n);
+    T_.begin(3);
     hipLaunchKernelGGL((k_rows<N>), g2, dim3(Rows<N>::THREADS), Rows<N>::LDS, st, a);
+    T_.end();
   }
   return launched();
 }
@@ -204,18 +270,19 @@ blink_status grid_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t st
   const long long n_img = (long long)p->n_time * p->n_chan;
   const bool uni = p->weighting == BLINK_UNIFORM;
   const size_t lds1 = Cols<N>::lds_bytes(true);
+  a.wtiles = (int)cdiv(N, Cols<N>::CPW);
+  hipLaunchKernelGGL(k_bounds, dim3((unsigned)n_img), dim3(256), 0, st, a);
   for (long long i0 = 0; i0 < n_img; i0 += chunk) {
     const int n = (int)std::min<long long>(chunk, n_img - i0);
     a.img0 = (int)i0; a.nimg = n;
-    hipLaunchKernelGGL(k_bounds, dim3(n), dim3(256), 0, st, a);
     const dim3 g1(cdiv(N, Cols<N>::CPW), n);
     if (uni)
       hipLaunchKernelGGL((k_grid_cols<N, MODE_GRID, true>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
     else
       hipLaunchKernelGGL((k_grid_cols<N, MODE_GRID, false>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
-    if (a.weight_sum || a.n_dropped)
-      hipLaunchKernelGGL(k_grid_finish, dim3(cdiv(n, 256)), dim3(256), 0, st, a);
   }
+  if (a.weight_sum || a.n_dropped)
+    hipLaunchKernelGGL(k_grid_finish, dim3(cdiv(n_img, 256)), dim3(256), 0, st, a, (int)n_img);
   return launched();
 }
 
@@ -225,10 +292,11 @@ blink_status adjoint_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t
   const bool uni = p->weighting == BLINK_UNIFORM;
   if (a.gains)
     hipLaunchKernelGGL(k_fill2, dim3(cdiv(a.B, 256)), dim3(256), 0, st, a.pacc, (size_t)a.B);
+  a.wtiles = (int)cdiv(N / 2, Cols<N>::CPW);
+  hipLaunchKernelGGL(k_bounds, dim3((unsigned)n_img), dim3(256), 0, st, a);
   for (long long i0 = 0; i0 < n_img; i0 += chunk) {
     const int n = (int)std::min<long long>(chunk, n_img - i0);
     a.img0 = (int)i0; a.nimg = n;
-    hipLaunchKernelGGL(k_bounds, dim3(n), dim3(256), 0, st, a);
     const dim3 g1(cdiv(N / 2, Cols<N>::CPW), n);
     const size_t ldsw = uni ? (size_t)Cols<N>::CPW * N * sizeof(int) : 0;
     if (uni)
@@ -356,9 +424,9 @@ blink_status blink_fft2d(const blink_c32* in, blink_c32* out, int32_t batch, int
 #undef BLINK_FFT_CALL
 }
 
-blink_status blink_image_batch(const blink_problem* p, const blink_inputs* in, float* images,
-                               float* weight_sum, void* workspace, size_t ws_bytes,
-                               blink_stream_t stream) {
+static blink_status image_batch_impl(const blink_problem* p, const blink_inputs* in, float* images,
+                                     float* weight_sum, void* workspace, size_t ws_bytes,
+                                     blink_stream_t stream, Timer* tm) {
   blink_status e = validate_problem(p, BLINK_CALL_IMAGE);
   if (e != BLINK_OK) return e;
   if ((e = validate_inputs(p, in)) != BLINK_OK) return e;
@@ -368,15 +436,35 @@ blink_status blink_image_batch(const blink_problem* p, const blink_inputs* in, f
   int chunk = 0;
   if ((e = check_ws(p, BLINK_CALL_IMAGE, workspace, ws_bytes, &chunk)) != BLINK_OK) return e;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  tm->st = st;
   Work w{};
   carve(p, BLINK_CALL_IMAGE, chunk, static_cast<char*>(workspace), &w);
-  run_sort(p, in, w, st);
+  run_sort(p, in, w, st, tm);
   ImgArgs a = make_args(p, in, w);
   a.images = images;
   a.weight_sum = weight_sum;
-#define BLINK_IMAGE_CALL(n) image_n<n>(p, a, chunk, st)
+#define BLINK_IMAGE_CALL(n) image_n<n>(p, a, chunk, st, tm)
   BLINK_DISPATCH_N(p->grid_n, BLINK_IMAGE_CALL)
 #undef BLINK_IMAGE_CALL
+}
+
+blink_status blink_image_batch(const blink_problem* p, const blink_inputs* in, float* images,
+                               float* weight_sum, void* workspace, size_t ws_bytes,
+                               blink_stream_t stream) {
+  Timer off;
+  return image_batch_impl(p, in, images, weight_sum, workspace, ws_bytes, stream, &off);
+}
+
+blink_status blink_image_batch_timed(const blink_problem* p, const blink_inputs* in,
+                                     float* images, float* weight_sum, void* workspace,
+                                     size_t ws_bytes, blink_stream_t stream,
+                                     blink_kernel_times* times) {
+  if (!times) return BLINK_E_ARG;
+  Timer tm;
+  tm.on = true;
+  blink_status e = image_batch_impl(p, in, images, weight_sum, workspace, ws_bytes, stream, &tm);
+  const blink_status c = tm.collect(times);
+  return e != BLINK_OK ? e : c;
 }
 
 blink_status blink_degrid_adjoint(const blink_problem* p, const blink_inputs* in,

@@ -184,9 +184,11 @@ struct ImgArgs {
   const int* perm;              // [T][B]
   const int* n_valid;           // [T]
   const int* n_unflagged;       // [T]
-  int* bnd;                     // [chunk][N + 2]
-  int* wacc;                    // [chunk] weight-sum accumulators
-  int* kacc;                    // [chunk] kept-baseline accumulators
+  int* bnd;                     // [T*C][N + 2]
+  int* wpart;                   // [T*C][wstride] weight-sum partials, one per column tile
+  int* kpart;                   // [T*C][wstride] kept-baseline partials, one per column tile
+  int wstride;                  // partial slots per image (>= tiles of any producer kernel)
+  int wtiles;                   // tiles written by the current producer kernel
   int img0, nimg;               // this chunk: images [img0, img0 + nimg)
   float2* half;                 // [chunk][N/2][M] column-transformed half spectrum
   float2* grid;                 // MODE_GRID: [T*C][N][N]
@@ -204,18 +206,15 @@ struct ImgArgs {
 };
 
 // bnd[c + N/2] = first sorted position j with clamp(rint(u_j s)) >= c for
-// c in [-N/2, N/2 + 1]; entry N + 1 is always n_valid. Also clears the
-// chunk's accumulators.
+// c in [-N/2, N/2 + 1]; entry N + 1 is always n_valid. One workgroup per image.
 __global__ void __launch_bounds__(256) k_bounds(ImgArgs a) {
-  const int li = blockIdx.x;
-  const int img = a.img0 + li;
+  const int img = blockIdx.x;
   const int t = img / a.C, ch = img - t * a.C;
   const double s = cells_per_metre(a.freq[ch], a.ndx);
   const int H = a.N / 2;
   const int nv = a.n_valid[t];
   const double* su = a.su + (size_t)t * a.B;
-  int* bnd = a.bnd + (size_t)li * (a.N + 2);
-  if (threadIdx.x == 0) { a.wacc[li] = 0; a.kacc[li] = 0; }
+  int* bnd = a.bnd + (size_t)img * (a.N + 2);
   auto col = [&](int j) -> int {
     const double x = rint(su[j] * s);
     return (int)fmin(fmax(x, (double)-H), (double)H);
@@ -227,6 +226,15 @@ __global__ void __launch_bounds__(256) k_bounds(ImgArgs a) {
   }
   const int clast = nv == 0 ? -H - 1 : col(nv - 1);
   for (int c = clast + 1 + (int)threadIdx.x; c <= H + 1; c += blockDim.x) bnd[c + H] = nv;
+}
+
+// Sum of the per-tile partials of one image (read by one wavefront; every
+// slot below wtiles was written by exactly one workgroup of the producer).
+__device__ __forceinline__ int sum_partials(const int* part, int img, int wstride, int wtiles, int lane) {
+  int v = 0;
+  for (int i = lane; i < wtiles; i += WAVE) v += part[(size_t)img * wstride + i];
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
 }
 
 // ============================================================== visibility load
@@ -298,10 +306,13 @@ __device__ __forceinline__ int grid_points(const ImgArgs& a, float2* buf, int* c
   return kept;
 }
 
+// u-cell columns (one wavefront each) per workgroup of the column kernels
+__host__ __device__ constexpr int cols_per_wg(int n) { return n <= 1024 ? 8 : (n <= 2048 ? 4 : 2); }
+
 template <int N>
 struct Cols {
   static constexpr int STRIDE = padded_len(N);                // complex per column buffer
-  static constexpr int CPW = N <= 1024 ? 8 : (N <= 2048 ? 4 : 2);  // columns (waves) per workgroup
+  static constexpr int CPW = cols_per_wg(N);
   static constexpr int THREADS = CPW * WAVE;
   static size_t lds_bytes(bool counts) {
     return (size_t)CPW * STRIDE * sizeof(float2) + (counts ? (size_t)CPW * N * sizeof(int) : 0);
@@ -339,7 +350,7 @@ __global__ void __launch_bounds__(Cols<N>::THREADS) k_grid_cols(ImgArgs a) {
 
   int kept_b = 0, wcontrib = 0;
   if (active && cs != H && cs != -H) {
-    const int* bnd = a.bnd + (size_t)li * (N + 2);
+    const int* bnd = a.bnd + (size_t)img * (N + 2);
     const int dlo = bnd[cs + H], dhi = bnd[cs + 1 + H];
     const int clo = bnd[-cs + H], chi = bnd[-cs + 1 + H];
     const int kd = grid_points<N, false, CNT>(a, buf, cnt, dlo, dhi, t, ch, s, lane);
@@ -367,9 +378,16 @@ __global__ void __launch_bounds__(Cols<N>::THREADS) k_grid_cols(ImgArgs a) {
     } else {
       wcontrib = mult * (kd + kc);
     }
-    if (lane == 0) {
-      atomicAdd(&a.wacc[li], wcontrib);
-      atomicAdd(&a.kacc[li], kept_b);
+  }
+  {
+    __shared__ int red[2 * CPW];
+    if (lane == 0) { red[wave] = wcontrib; red[CPW + wave] = kept_b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int ws = 0, ks = 0;
+      for (int i = 0; i < CPW; ++i) { ws += red[i]; ks += red[CPW + i]; }
+      a.wpart[(size_t)img * a.wstride + blockIdx.x] = ws;
+      a.kpart[(size_t)img * a.wstride + blockIdx.x] = ks;
     }
   }
 
@@ -386,7 +404,6 @@ __global__ void __launch_bounds__(Cols<N>::THREADS) k_grid_cols(ImgArgs a) {
       }
     }
   } else {
-    __syncthreads();
     // write the CPW-column tile row by row (CPW consecutive cells per row)
     const int c0 = blockIdx.x * CPW;
     float2* g = a.grid + (size_t)img * N * N;
@@ -401,13 +418,17 @@ __global__ void __launch_bounds__(Cols<N>::THREADS) k_grid_cols(ImgArgs a) {
   }
 }
 
-__global__ void k_grid_finish(ImgArgs a) {
-  const int li = blockIdx.x * blockDim.x + threadIdx.x;
-  if (li >= a.nimg) return;
-  const int img = a.img0 + li;
+__global__ void k_grid_finish(ImgArgs a, int n_img) {
+  const int img = blockIdx.x * blockDim.x + threadIdx.x;
+  if (img >= n_img) return;
   const int t = img / a.C;
-  if (a.weight_sum) a.weight_sum[img] = (float)a.wacc[li];
-  if (a.n_dropped) a.n_dropped[img] = a.n_unflagged[t] - a.kacc[li];
+  int w = 0, k = 0;
+  for (int i = 0; i < a.wtiles; ++i) {
+    w += a.wpart[(size_t)img * a.wstride + i];
+    k += a.kpart[(size_t)img * a.wstride + i];
+  }
+  if (a.weight_sum) a.weight_sum[img] = (float)w;
+  if (a.n_dropped) a.n_dropped[img] = a.n_unflagged[t] - k;
 }
 
 // ============================================================== row pass
@@ -438,7 +459,7 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
   const int M = a.M;
   const int npair = M / 2;
   const int p0 = blockIdx.x * PPW;            // first row pair of this workgroup
-  const int W = a.wacc[li];
+  const int W = sum_partials(a.wpart, img, a.wstride, a.wtiles, lane);
   const float scale = a.norm ? (W > 0 ? 1.0f / (float)W : 0.0f) : 1.0f;
   if (blockIdx.x == 0 && threadIdx.x == 0 && a.weight_sum) a.weight_sum[img] = (float)W;
 
@@ -525,6 +546,7 @@ __global__ void __launch_bounds__(Fft2<N>::THREADS) k_fft_cols(float2* data) {
 template <int N, bool UNI>
 __global__ void __launch_bounds__(Cols<N>::THREADS) k_weights(ImgArgs a) {
   extern __shared__ int lw_raw[];
+  __shared__ int red[Cols<N>::CPW];
   constexpr int H = N / 2;
   constexpr int CPW = Cols<N>::CPW;
   const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
@@ -532,40 +554,49 @@ __global__ void __launch_bounds__(Cols<N>::THREADS) k_weights(ImgArgs a) {
   const int img = a.img0 + li;
   const int t = img / a.C, ch = img - t * a.C;
   const int cs = blockIdx.x * CPW + wave;
-  if (cs >= H) return;
-  int* cnt = lw_raw + wave * N;
-  const double s = cells_per_metre(a.freq[ch], a.ndx);
-  if (UNI) {
-    for (int r = lane; r < N; r += WAVE) cnt[r] = 0;
-    wave_sync();
-  }
-  const int* bnd = a.bnd + (size_t)li * (N + 2);
-  const size_t tb = (size_t)t * a.B;
-  int kept = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    const int c = pass == 0 ? cs : -cs;
-    const int lo = bnd[c + H], hi = bnd[c + 1 + H];
-    for (int j = lo + lane; j < hi; j += WAVE) {
-      const double iv = rint(a.sv[tb + j] * s);
-      if (fabs(iv) < (double)H) {
-        ++kept;
-        if (UNI) {
-          int r = (int)iv;
-          if (pass) r = -r;
-          atomicAdd(&cnt[r < 0 ? r + N : r], 1);
+  int w = 0;
+  if (cs < H) {
+    int* cnt = lw_raw + wave * N;
+    const double s = cells_per_metre(a.freq[ch], a.ndx);
+    if (UNI) {
+      for (int r = lane; r < N; r += WAVE) cnt[r] = 0;
+      wave_sync();
+    }
+    const int* bnd = a.bnd + (size_t)img * (N + 2);
+    const size_t tb = (size_t)t * a.B;
+    int kept = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+      const int c = pass == 0 ? cs : -cs;
+      const int lo = bnd[c + H], hi = bnd[c + 1 + H];
+      for (int j = lo + lane; j < hi; j += WAVE) {
+        const double iv = rint(a.sv[tb + j] * s);
+        if (fabs(iv) < (double)H) {
+          ++kept;
+          if (UNI) {
+            int r = (int)iv;
+            if (pass) r = -r;
+            atomicAdd(&cnt[r < 0 ? r + N : r], 1);
+          }
         }
       }
     }
+    w = kept;
+    if (UNI) {
+      wave_sync();
+      int occ = 0;
+      for (int r = lane; r < N; r += WAVE) occ += cnt[r] > 0;
+      w = occ;
+    }
+    for (int o = WAVE / 2; o > 0; o >>= 1) w += __shfl_xor(w, o);
+    w *= (cs > 0 ? 2 : 1);
   }
-  int w = kept;
-  if (UNI) {
-    wave_sync();
-    int occ = 0;
-    for (int r = lane; r < N; r += WAVE) occ += cnt[r] > 0;
-    w = occ;
+  if (lane == 0) red[wave] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ws = 0;
+    for (int i = 0; i < CPW; ++i) ws += red[i];
+    a.wpart[(size_t)img * a.wstride + blockIdx.x] = ws;
   }
-  for (int o = WAVE / 2; o > 0; o >>= 1) w += __shfl_xor(w, o);
-  if (lane == 0) atomicAdd(&a.wacc[li], (cs > 0 ? 2 : 1) * w);
 }
 
 // Adjoint of k_rows: image-gradient rows m, m+1 (zero outside the cutout,
@@ -585,7 +616,7 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows_adj(ImgArgs a) {
   const int M = a.M;
   const int npair = M / 2;
   const int p0 = blockIdx.x * PPW;
-  const int W = a.wacc[li];
+  const int W = sum_partials(a.wpart, img, a.wstride, a.wtiles, lane);
   const float scale = a.norm ? (W > 0 ? 1.0f / (float)W : 0.0f) : 1.0f;
   const int pair = p0 + wave;
   if (pair < npair) {
@@ -651,7 +682,7 @@ __global__ void __launch_bounds__(Cols<N>::THREADS) k_cols_adj(ImgArgs a) {
     q = q < 0 ? q + N : q;
     buf[pad(q)] = srcc[m];
   }
-  const int* bnd = a.bnd + (size_t)li * (N + 2);
+  const int* bnd = a.bnd + (size_t)img * (N + 2);
   const int dlo = bnd[cs + H], dhi = bnd[cs + 1 + H];
   const int clo = bnd[-cs + H], chi = bnd[-cs + 1 + H];
   const size_t tb = (size_t)t * a.B;
