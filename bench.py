@@ -74,6 +74,103 @@ def cpu_baseline(w, vis_cpu, sample, cores):
     return len(jobs) / dt, dt
 
 
+# ---------------------------------------------------------------- rocprof summaries
+PROFILE_CMDS = {
+    "stats": "rocprofv3 --kernel-trace --stats --output-format csv -d OUT/stats -o bench -- "
+             "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'blink|copyBuffer' --output-format csv "
+             "-d OUT/pmc_FETCH_SIZE -o bench -- python3 bench.py --timesteps 10 --steps 1 --warmup 0 --no-cpu-baseline",
+    "write": "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'blink|copyBuffer' --output-format csv "
+             "-d OUT/pmc_WRITE_SIZE -o bench -- python3 bench.py --timesteps 10 --steps 1 --warmup 0 --no-cpu-baseline",
+    "copy_fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'blink|copyBuffer' --output-format csv "
+                  "-d OUT/pmc_copy_FETCH_SIZE -o copy -- python3 bench.py --copy-calibration",
+    "copy_write": "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'blink|copyBuffer' --output-format csv "
+                  "-d OUT/pmc_copy_WRITE_SIZE -o copy -- python3 bench.py --copy-calibration",
+}
+KERNEL_KEYS = {"grid_cols": "k_grid_cols<1024, 0", "rows": "k_rows<1024>"}
+
+
+def _csv(path):
+    import csv
+    import glob
+    files = glob.glob(path)
+    if not files:
+        raise SystemExit(f"missing rocprof output: {path}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def _counter_mean(rows, key, counter):
+    v = [float(r["Counter_Value"]) for r in rows if key in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    return (sum(v) / len(v), len(v)) if v else (None, 0)
+
+
+def summarize(out_dir):
+    """Write profiles/ summaries from the rocprofv3 outputs under out_dir (CPU only)."""
+    prof = os.path.join(ROOT, "profiles")
+    os.makedirs(prof, exist_ok=True)
+    digest = _csrc_digest()
+    stats = _csv(os.path.join(out_dir, "stats", "*_kernel_stats.csv"))
+    tot = sum(float(r["TotalDurationNs"]) for r in stats if "blink" in r["Name"])
+    lines = ["# rocprofv3 kernel statistics: widefield 1024^2 -> 512^2 image batches", "",
+             "Workload: 128 tiles (8128 baselines), 768 channels x 10 timesteps per step (7,680 images), "
+             "natural weighting; 5 timed steps + 1 warm-up.", "",
+             "Command (from the repository root, with OUT the output folder):", "",
+             "    " + PROFILE_CMDS["stats"], "",
+             f"Library sources digest: `{digest}`", "",
+             "| kernel | calls | avg us | min us | max us | share of blink time |",
+             "|---|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        if "blink" not in r["Name"]:
+            continue
+        lines.append(f"| `{r['Name'].replace('|', '/')}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{100 * float(r['TotalDurationNs']) / tot:.1f}% |")
+    with open(os.path.join(prof, "k_grid_cols_k_rows_widefield1024_kernel_stats.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    fe = _csv(os.path.join(out_dir, "pmc_FETCH_SIZE", "*_counter_collection.csv"))
+    wr = _csv(os.path.join(out_dir, "pmc_WRITE_SIZE", "*_counter_collection.csv"))
+    cfe = _csv(os.path.join(out_dir, "pmc_copy_FETCH_SIZE", "*_counter_collection.csv"))
+    cwr = _csv(os.path.join(out_dir, "pmc_copy_WRITE_SIZE", "*_counter_collection.csv"))
+    copy_bytes = 1 << 30
+    cf, _ = _counter_mean(cfe, "copyBuffer", "FETCH_SIZE")
+    cw, _ = _counter_mean(cwr, "copyBuffer", "WRITE_SIZE")
+    f_fetch = copy_bytes / (cf * 1024.0)
+    f_write = copy_bytes / (cw * 1024.0)
+    imgs = 512
+    res = {"workload": "widefield 1024^2 -> 512^2, 8128 baselines, 512 images per launch",
+           "csrc_digest": digest, "copy_calibration": {"bytes": copy_bytes, "FETCH_SIZE_KiB": cf,
+                                                      "WRITE_SIZE_KiB": cw, "fetch_scale": f_fetch,
+                                                      "write_scale": f_write},
+           "kernels": {}}
+    md = ["# HBM traffic per dispatch (rocprofv3 FETCH_SIZE / WRITE_SIZE)", "",
+          "Counters in KiB per dispatch, scaled by what the same counter reads for a plain 1 GiB "
+          "device copy (`__amd_rocclr_copyBuffer`).", "", "Commands (from the repository root):", ""]
+    md += ["    " + PROFILE_CMDS[k] for k in ("fetch", "write", "copy_fetch", "copy_write")]
+    md += ["", f"Copy calibration: FETCH_SIZE {cf:.1f} KiB and WRITE_SIZE {cw:.1f} KiB for 1 GiB moved "
+           f"-> scale {f_fetch:.4f} (fetch), {f_write:.4f} (write).", "",
+           f"Library sources digest: `{digest}`", "",
+           "| kernel | dispatches | FETCH KiB | WRITE KiB | HBM bytes / launch (scaled) | per image | algorithmic per image |",
+           "|---|---|---|---|---|---|---|"]
+    alg = {"grid_cols": 8128 * 8 + 512 * 512 * 8, "rows": 512 * 512 * 8 + 512 * 512 * 4}
+    for name, key in KERNEL_KEYS.items():
+        fm, n = _counter_mean(fe, key, "FETCH_SIZE")
+        wm, _ = _counter_mean(wr, key, "WRITE_SIZE")
+        tb = (fm * f_fetch + wm * f_write) * 1024.0
+        res["kernels"][name] = {"FETCH_SIZE_KiB": fm, "WRITE_SIZE_KiB": wm, "dispatches": n,
+                                "hbm_bytes_per_launch": tb, "images_per_launch": imgs}
+        md.append(f"| {name} (`{key}`) | {n} | {fm:.1f} | {wm:.1f} | {tb:.4g} | {tb / imgs:.4g} | {alg[name]} |")
+    dom = "grid_cols"
+    res["kernel"] = dom
+    res["hbm_bytes_per_launch"] = res["kernels"][dom]["hbm_bytes_per_launch"]
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(res, f, indent=1)
+    with open(TRAFFIC_FILE.replace(".json", ".md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    print(json.dumps(res))
+
+
 # ---------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -81,12 +178,19 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--timesteps-per-step", type=int, default=10)
+    ap.add_argument("--timesteps", type=int, default=100,
+                    help="timesteps of the job generated into HBM (100 = the whole workload)")
     ap.add_argument("--chunk", type=int, default=0, help="images per internal chunk (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration for profiling)")
+    ap.add_argument("--summarize", metavar="ROCPROF_OUT",
+                    help="write the profiles/ summaries from rocprofv3 output (no GPU needed)")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize)
+        return
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -111,7 +215,7 @@ def main():
 
     blink.load_library()
     TT = args.timesteps_per_step
-    w = synth.widefield(n_time=100, n_chan=768)
+    w = synth.widefield(n_time=max(TT, args.timesteps), n_chan=768)
     n_batches = w.n_time // TT
     t_gen = time.perf_counter()
     vis = synth.visibilities(w, device=dev)                                # [100][768][8128] c64, 5.0 GB
