@@ -42,6 +42,7 @@ struct Work {
   double* sv;
   int* perm;
   int* bnd;
+  int* ncz;
   int* wpart;
   int* kpart;
   int wstride;
@@ -80,6 +81,7 @@ size_t carve(const blink_problem* p, int call, int chunk, char* base, Work* w) {
   x.perm = (int*)take(T * B * 4);
   const size_t n_img = (size_t)p->n_time * (size_t)p->n_chan;
   x.bnd = (int*)take(n_img * (N + 2) * 4);
+  x.ncz = (int*)take(n_img * 4);
   x.wstride = (int)((N + cols_per_wg((int)N) - 1) / cols_per_wg((int)N));
   x.wpart = (int*)take(n_img * x.wstride * 4);
   x.kpart = (int*)take(n_img * x.wstride * 4);
@@ -232,7 +234,7 @@ ImgArgs make_args(const blink_problem* p, const blink_inputs* in, const Work& w)
   a.n_ant = p->n_ant;
   a.su = w.su; a.sv = w.sv; a.perm = w.perm;
   a.n_unflagged = w.counters; a.n_valid = w.counters + p->n_time;
-  a.bnd = w.bnd; a.wpart = w.wpart; a.kpart = w.kpart; a.wstride = w.wstride;
+  a.bnd = w.bnd; a.ncz = w.ncz; a.wpart = w.wpart; a.kpart = w.kpart; a.wstride = w.wstride;
   a.half = w.half; a.gamma = w.gamma; a.pacc = w.pacc;
   return a;
 }
@@ -250,7 +252,8 @@ blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t s
   for (long long i0 = 0; i0 < n_img; i0 += chunk) {
     const int n = (int)std::min<long long>(chunk, n_img - i0);
     a.img0 = (int)i0; a.nimg = n;
-    const dim3 g1(cdiv(N / 2, Cols<N>::CPW), n);
+    a.ntiles = (int)cdiv(N / 2, Cols<N>::CPW);
+    const dim3 g1((unsigned)(cdiv(n, 8) * 8LL * a.ntiles));
     T_.begin(2);
     if (uni)
       hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, true>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
@@ -275,7 +278,8 @@ blink_status grid_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t st
   for (long long i0 = 0; i0 < n_img; i0 += chunk) {
     const int n = (int)std::min<long long>(chunk, n_img - i0);
     a.img0 = (int)i0; a.nimg = n;
-    const dim3 g1(cdiv(N, Cols<N>::CPW), n);
+    a.ntiles = (int)cdiv(N, Cols<N>::CPW);
+    const dim3 g1((unsigned)(cdiv(n, 8) * 8LL * a.ntiles));
     if (uni)
       hipLaunchKernelGGL((k_grid_cols<N, MODE_GRID, true>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
     else

@@ -185,6 +185,8 @@ struct ImgArgs {
   const int* n_valid;           // [T]
   const int* n_unflagged;       // [T]
   int* bnd;                     // [T*C][N + 2]
+  int* ncz;                     // [T*C] u-cell columns 0..ncz-1 may be non-empty; the rest are zero
+  int ntiles;                   // column tiles per image of the current column kernel
   int* wpart;                   // [T*C][wstride] weight-sum partials, one per column tile
   int* kpart;                   // [T*C][wstride] kept-baseline partials, one per column tile
   int wstride;                  // partial slots per image (>= tiles of any producer kernel)
@@ -226,6 +228,8 @@ __global__ void __launch_bounds__(256) k_bounds(ImgArgs a) {
   }
   const int clast = nv == 0 ? -H - 1 : col(nv - 1);
   for (int c = clast + 1 + (int)threadIdx.x; c <= H + 1; c += blockDim.x) bnd[c + H] = nv;
+  // every entry lies in a column |c| <= max(|first|, |last|) of the sorted order
+  if (threadIdx.x == 0) a.ncz[img] = nv == 0 ? 0 : min(H, max(clast, -col(0)) + 1);
 }
 
 // Sum of the per-tile partials of one image (read by one wavefront; every
@@ -268,31 +272,37 @@ __device__ __forceinline__ float2 load_vis(const ImgArgs& a, size_t off, int b, 
   return v;
 }
 
-// Grid the points of sorted positions [lo, hi) into one column buffer:
-// value V' at row i_v (CONJ = false) or conj(V') at row -i_v (CONJ = true).
-// Only this wavefront touches the column, so the LDS adds happen in a fixed
-// order (chunks of the sorted list in sequence, lanes in LDS order).
-template <int N, bool CONJ, bool COUNT>
-__device__ __forceinline__ int grid_points(const ImgArgs& a, float2* buf, int* cnt, int lo, int hi,
-                                           int t, int ch, double s, int lane) {
+// Grid the column's entries: sorted positions [dlo, dhi) add V' at row i_v,
+// positions [clo, chi) (the mirror column) add conj(V') at row -i_v. Both
+// ranges are walked as one list, 64 entries per step, so each step issues its
+// loads together. Only this wavefront touches the column, so the LDS adds
+// happen in a fixed order (steps in sequence, lanes in LDS order within a
+// step). Returns the kept direct and conjugate entries.
+template <int N, bool COUNT>
+__device__ __forceinline__ int2 grid_points(const ImgArgs& a, float2* buf, int* cnt, int dlo, int dhi,
+                                            int clo, int chi, int t, int ch, double s, int lane) {
   const size_t tb = (size_t)t * a.B;
   const size_t vb = ((size_t)t * a.C + ch) * a.B;
-  int kept = 0;
-  for (int j0 = lo; j0 < hi; j0 += WAVE) {
-    const int j = j0 + lane;
-    bool ok = j < hi;
+  const int nd = dhi - dlo;
+  const int total = nd + (chi - clo);
+  int kd = 0, kc = 0;
+  for (int i0 = 0; i0 < total; i0 += WAVE) {
+    const int i = i0 + lane;
+    bool ok = i < total;
+    const bool conj = i >= nd;
     int row = 0;
     float2 val = make_float2(0.f, 0.f);
     if (ok) {
+      const int j = conj ? clo + (i - nd) : dlo + i;
       const double iv = rint(a.sv[tb + j] * s);
+      const int b = a.perm[tb + j];
       ok = fabs(iv) < (double)(N / 2);
       if (ok) {
-        const int b = a.perm[tb + j];
         int r = (int)iv;
-        if (CONJ) r = -r;
+        if (conj) r = -r;
         row = r < 0 ? r + N : r;
         val = load_vis(a, vb + b, b, ch);
-        if (CONJ) val.y = -val.y;
+        if (conj) val.y = -val.y;
       }
     }
     if (ok) {
@@ -301,21 +311,39 @@ __device__ __forceinline__ int grid_points(const ImgArgs& a, float2* buf, int* c
       atomicAdd(&p->y, val.y);
       if (COUNT) atomicAdd(&cnt[row], 1);
     }
-    kept += __popcll(__ballot(ok));
+    kd += __popcll(__ballot(ok && !conj));
+    kc += __popcll(__ballot(ok && conj));
   }
-  return kept;
+  return make_int2(kd, kc);
 }
 
 // u-cell columns (one wavefront each) per workgroup of the column kernels
 __host__ __device__ constexpr int cols_per_wg(int n) { return n <= 1024 ? 8 : (n <= 2048 ? 4 : 2); }
+
+// Twiddle table staged in LDS (one copy per workgroup) where it fits beside
+// the transform buffers without lowering occupancy.
+template <int N>
+struct TwLds { static constexpr bool ON = N <= 1024; };
+
+template <int N>
+__device__ __forceinline__ const float2* stage_twiddles(float2* lds_tw) {
+  if constexpr (TwLds<N>::ON) {
+    const float2* g = TwTable<N>::get();
+    for (int i = threadIdx.x; i < N; i += blockDim.x) lds_tw[i] = g[i];
+    return lds_tw;      // visible after the caller's next __syncthreads
+  } else {
+    return TwTable<N>::get();
+  }
+}
 
 template <int N>
 struct Cols {
   static constexpr int STRIDE = padded_len(N);                // complex per column buffer
   static constexpr int CPW = cols_per_wg(N);
   static constexpr int THREADS = CPW * WAVE;
+  static constexpr int TW = TwLds<N>::ON ? N : 0;             // complex twiddles in LDS
   static size_t lds_bytes(bool counts) {
-    return (size_t)CPW * STRIDE * sizeof(float2) + (counts ? (size_t)CPW * N * sizeof(int) : 0);
+    return (size_t)(CPW * STRIDE + TW) * sizeof(float2) + (counts ? (size_t)CPW * N * sizeof(int) : 0);
   }
 };
 
@@ -323,25 +351,43 @@ struct Cols {
 // per column. MODE_IMAGE: columns 0..N/2-1 (the half spectrum), transform
 // along v, rows of the cutout written to `half`. MODE_GRID: all N columns,
 // weighted grid and counts written out.
+// The 1D grid is laid out so that all column tiles of an image share one XCD
+// (workgroup L runs on XCD L mod 8): the image's visibility row and the
+// timestep's sorted lists are then fetched into a single L2.
 template <int N, int MODE, bool UNI>
 __global__ void __launch_bounds__(Cols<N>::THREADS) k_grid_cols(ImgArgs a) {
   extern __shared__ float4 lds_raw[];
+  __shared__ int red[2 * Cols<N>::CPW];
   constexpr int H = N / 2;
   constexpr int CPW = Cols<N>::CPW;
+  constexpr bool CNT = UNI || MODE == MODE_GRID;
+  const int L = blockIdx.x;
+  const int r8 = L >> 3;
+  const int li = (r8 / a.ntiles) * 8 + (L & 7);
+  const int tile = r8 % a.ntiles;
+  if (li >= a.nimg) return;                          // padding of the last group of 8 images
   float2* lds = reinterpret_cast<float2*>(lds_raw);
-  int* lcnt = reinterpret_cast<int*>(lds + CPW * Cols<N>::STRIDE);
+  float2* ltw = lds + CPW * Cols<N>::STRIDE;
+  int* lcnt = reinterpret_cast<int*>(ltw + Cols<N>::TW);
   const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-  const int li = blockIdx.y;
   const int img = a.img0 + li;
   const int t = img / a.C, ch = img - t * a.C;
-  const int col = blockIdx.x * CPW + wave;          // MODE_IMAGE: 0..H-1, MODE_GRID: 0..N-1
-  const int ncols = MODE == MODE_IMAGE ? H : N;
+  const int c0 = tile * CPW;
+  const int ncols = MODE == MODE_IMAGE ? min(H, a.ncz[img]) : N;
+  if (c0 >= ncols) {                                 // the whole tile is empty
+    if (threadIdx.x == 0) {
+      a.wpart[(size_t)img * a.wstride + tile] = 0;
+      a.kpart[(size_t)img * a.wstride + tile] = 0;
+    }
+    return;
+  }
+  const int col = c0 + wave;                        // MODE_IMAGE: 0..H-1, MODE_GRID: 0..N-1
   const bool active = col < ncols;
   const int cs = MODE == MODE_IMAGE ? col : (col < H ? col : col - N);  // signed u cell
-  constexpr bool CNT = UNI || MODE == MODE_GRID;
   float2* buf = lds + wave * Cols<N>::STRIDE;
   int* cnt = CNT ? lcnt + wave * N : nullptr;
   const double s = cells_per_metre(a.freq[ch], a.ndx);
+  const float2* tw = MODE == MODE_IMAGE ? stage_twiddles<N>(ltw) : nullptr;
 
   for (int r = lane; r < Cols<N>::STRIDE; r += WAVE) buf[r] = make_float2(0.f, 0.f);
   if (CNT)
@@ -353,8 +399,8 @@ __global__ void __launch_bounds__(Cols<N>::THREADS) k_grid_cols(ImgArgs a) {
     const int* bnd = a.bnd + (size_t)img * (N + 2);
     const int dlo = bnd[cs + H], dhi = bnd[cs + 1 + H];
     const int clo = bnd[-cs + H], chi = bnd[-cs + 1 + H];
-    const int kd = grid_points<N, false, CNT>(a, buf, cnt, dlo, dhi, t, ch, s, lane);
-    const int kc = grid_points<N, true, CNT>(a, buf, cnt, clo, chi, t, ch, s, lane);
+    const int2 k2 = grid_points<N, CNT>(a, buf, cnt, dlo, dhi, clo, chi, t, ch, s, lane);
+    const int kd = k2.x, kc = k2.y;
     wave_sync();
     // baselines counted once: the direct entry of every cell column, plus the
     // conjugate entries of columns whose mirror the image path never visits
@@ -379,21 +425,18 @@ __global__ void __launch_bounds__(Cols<N>::THREADS) k_grid_cols(ImgArgs a) {
       wcontrib = mult * (kd + kc);
     }
   }
-  {
-    __shared__ int red[2 * CPW];
-    if (lane == 0) { red[wave] = wcontrib; red[CPW + wave] = kept_b; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int ws = 0, ks = 0;
-      for (int i = 0; i < CPW; ++i) { ws += red[i]; ks += red[CPW + i]; }
-      a.wpart[(size_t)img * a.wstride + blockIdx.x] = ws;
-      a.kpart[(size_t)img * a.wstride + blockIdx.x] = ks;
-    }
+  if (lane == 0) { red[wave] = wcontrib; red[CPW + wave] = kept_b; }
+  __syncthreads();                                   // also publishes the LDS twiddles
+  if (threadIdx.x == 0) {
+    int ws = 0, ks = 0;
+    for (int i = 0; i < CPW; ++i) { ws += red[i]; ks += red[CPW + i]; }
+    a.wpart[(size_t)img * a.wstride + tile] = ws;
+    a.kpart[(size_t)img * a.wstride + tile] = ks;
   }
 
   if (MODE == MODE_IMAGE) {
     if (active) {
-      wave_fft<N, +1>(buf, lane, TwTable<N>::get());
+      wave_fft<N, +1>(buf, lane, tw);
       // rows of the cutout: output row m holds v-frequency q = (m - M/2) mod N
       float2* dst = a.half + ((size_t)li * H + col) * a.M;
       const int M = a.M;
@@ -405,7 +448,6 @@ __global__ void __launch_bounds__(Cols<N>::THREADS) k_grid_cols(ImgArgs a) {
     }
   } else {
     // write the CPW-column tile row by row (CPW consecutive cells per row)
-    const int c0 = blockIdx.x * CPW;
     float2* g = a.grid + (size_t)img * N * N;
     int* gc = a.counts ? a.counts + (size_t)img * N * N : nullptr;
     for (int e = threadIdx.x; e < N * CPW; e += blockDim.x) {
@@ -437,7 +479,8 @@ struct Rows {
   static constexpr int STRIDE = padded_len(N) + 4;   // +4 complex shifts buffers across banks
   static constexpr int PPW = N <= 1024 ? 8 : (N <= 2048 ? 4 : 2);  // row pairs (waves) per WG
   static constexpr int THREADS = PPW * WAVE;
-  static constexpr size_t LDS = (size_t)PPW * STRIDE * sizeof(float2);
+  static constexpr int TW = TwLds<N>::ON ? N : 0;
+  static constexpr size_t LDS = (size_t)(PPW * STRIDE + TW) * sizeof(float2);
 };
 
 // Inverse transform along u of two cutout rows per wavefront. The half
@@ -459,15 +502,17 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
   const int M = a.M;
   const int npair = M / 2;
   const int p0 = blockIdx.x * PPW;            // first row pair of this workgroup
+  const int nz = min(H, a.ncz[img]);          // columns >= nz of the half spectrum are zero
   const int W = sum_partials(a.wpart, img, a.wstride, a.wtiles, lane);
   const float scale = a.norm ? (W > 0 ? 1.0f / (float)W : 0.0f) : 1.0f;
   if (blockIdx.x == 0 && threadIdx.x == 0 && a.weight_sum) a.weight_sum[img] = (float)W;
+  const float2* tw = stage_twiddles<N>(lds + PPW * ST);
 
   const float4* src = reinterpret_cast<const float4*>(a.half + (size_t)li * H * M);
   for (int e = threadIdx.x; e < H * PPW; e += blockDim.x) {
     const int k = e / PPW, p = e % PPW;
     if (p0 + p < npair) {
-      const float4 ab = src[((size_t)k * M + 2 * (p0 + p)) / 2];
+      const float4 ab = k < nz ? src[((size_t)k * M + 2 * (p0 + p)) / 2] : make_float4(0.f, 0.f, 0.f, 0.f);
       float2* z = lds + p * ST;
       if (k == 0) {
         z[pad(0)] = make_float2(ab.x, ab.z);
@@ -482,7 +527,7 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
   const int pair = p0 + wave;
   if (pair >= npair) return;
   float2* z = lds + wave * ST;
-  wave_fft<N, +1>(z, lane, TwTable<N>::get());
+  wave_fft<N, +1>(z, lane, tw);
   float* r0 = a.images + ((size_t)img * M + 2 * pair) * M;
   float* r1 = r0 + M;
   for (int l = lane; l < M; l += WAVE) {
