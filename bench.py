@@ -194,18 +194,281 @@ def summarize(out_dir):
     print(json.dumps(res))
 
 
+# ---------------------------------------------------------------- workloads
+def _setup(args, synth):
+    """(workload, timesteps per step, channels per step) for --workload."""
+    k = args.workload
+    if k == "widefield":
+        TT = args.timesteps_per_step or 10
+        return synth.widefield(n_time=max(TT, args.timesteps or 100), n_chan=768), TT
+    if k == "plain":
+        return synth.plain_single(n_time=1), 1
+    if k == "allsky":
+        T = args.timesteps or 1000
+        return synth.station_allsky(n_time=T, n_chan=32), args.timesteps_per_step or T
+    if k == "precision":
+        TT = args.timesteps_per_step or 1
+        return synth.precision_station(n_time=max(TT, args.timesteps or 5), n_chan=384), TT
+    raise SystemExit(f"unknown workload {k}")
+
+
+DESCRIPTION = {
+    "widefield": "widefield 128 tiles (8128 baselines), 768 ch x 100 timesteps, 1024^2 grid -> 512^2 cutout, natural weighting",
+    "plain": "plain single image, 32 antennas (496 baselines), 1 ch at 160 MHz, 128^2, natural weighting",
+    "allsky": "station all-sky, 256 antennas (32640 baselines), 32 ch x 1000 timesteps (32,000 images), 180^2, uniform weighting, 2-10% flagged per timestep",
+    "precision": "precision, 256 tiles in 5 km (32640 baselines), 384 ch x 50 timesteps, 2048^2, uniform weighting",
+    "diff": "differentiation, widefield layout, 32 ch x 10 timesteps (320 images) 1024^2 -> 512^2, gains, loss ||I - I_model||^2",
+}
+
+
+def _timed_steps(blink, torch, args, run):
+    """Warm-up, then K timed calls of run(k, times); returns (total ms, per-class ms and launches)."""
+    times = blink.KernelTimes()
+    for k in range(args.warmup):
+        run(k, None)
+    torch.cuda.synchronize()
+    acc_ms, acc_n = [0.0] * 4, [0] * 4
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for k in range(args.steps):
+        run(k, times)
+        for c in range(4):
+            acc_ms[c] += times.ms[c]
+            acc_n[c] += times.launches[c]
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1), acc_ms, acc_n
+
+
+def _roofline(blink, acc_ms, acc_n, per_image, imgs_timed, digest_ok_kernel=None):
+    classes = blink.KCLASS
+    dom = max(range(4), key=lambda c: acc_ms[c])
+    name = classes[dom]
+    mean_ms = acc_ms[dom] / max(acc_n[dom], 1)
+    bytes_per_launch = per_image.get(name, 0) * imgs_timed / max(acc_n[dom], 1)
+    achieved = bytes_per_launch / (mean_ms * 1e-3) / 1e9 if mean_ms > 0 else 0.0
+    traffic = None
+    if digest_ok_kernel and os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("csrc_digest") == _csrc_digest() and name in tr.get("kernels", {}):
+            traffic = tr["kernels"][name].get("hbm_bytes_per_launch")
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": name, "mean_launch_ms": round(mean_ms, 5),
+            "algorithmic_bytes_per_launch": int(bytes_per_launch),
+            "images_per_launch": round(imgs_timed / max(acc_n[dom], 1), 2)}
+
+
+def bench_images(args, np, torch, blink, synth, dev):
+    w, TT = _setup(args, synth)
+    n_batches = w.n_time // TT
+    t_gen = time.perf_counter()
+    vis = synth.visibilities(w, device=dev)
+    uvw = torch.from_numpy(w.uvw_m).to(dev)
+    freq = torch.from_numpy(w.freq_hz).to(dev)
+    flags = None if w.flags is None else torch.from_numpy(w.flags).to(dev)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    n_img = TT * w.n_chan
+    M, N, H, B = w.out_n, w.grid_n, w.grid_n // 2, w.n_bl
+    images = torch.empty((n_img, M, M), dtype=torch.float32, device=dev)   # reused per step
+    ws_cache = {}
+
+    def make_run(v, scale, vbytes):
+        p = blink.blink.make_problem(v[:TT], uvw[:TT], freq, N, w.pixscale, M, w.weighting, w.norm,
+                                     None, args.chunk)
+        ws_cache[vbytes] = ws = blink.workspace(p, blink.CALL_IMAGE, dev)
+
+        def run(k, tm):
+            b = k % n_batches
+            sl = slice(b * TT, (b + 1) * TT)
+            blink.image_batch(v[sl], uvw[sl], freq, grid_n=N, pixscale=w.pixscale, out_n=M,
+                              weighting=w.weighting, norm=w.norm, flags=None if flags is None else flags[sl],
+                              vis_scale=scale, chunk_images=args.chunk, images=images, ws=ws, times=tm)
+        return run
+
+    ncz = np.concatenate([nonzero_columns(w, slice(b * TT, (b + 1) * TT))
+                          for b in range(min(args.steps, n_batches))])
+    unflagged = (B if w.flags is None else
+                 float(np.mean([(w.flags[t] == 0).sum() for t in range(min(args.steps, n_batches) * TT)])))
+    ncz_mean = float(ncz.mean())
+
+    def measure(v, scale, vbytes):
+        total_ms, acc_ms, acc_n = _timed_steps(blink, torch, args, make_run(v, scale, vbytes))
+        per_image = {"grid_cols": unflagged * vbytes + ncz_mean * M * 8,
+                     "rows": ncz_mean * M * 8 + M * M * 4}
+        img_per_s = n_img * args.steps / (total_ms / 1e3)
+        roof = _roofline(blink, acc_ms, acc_n, per_image, n_img * args.steps,
+                         digest_ok_kernel=args.workload == "widefield" and vbytes == 8)
+        path_bytes = per_image["grid_cols"] + per_image["rows"]
+        return {"images_per_s": img_per_s, "ms_per_step": total_ms / args.steps, "roofline": roof,
+                "kernel_ms_per_step": {blink.KCLASS[c]: round(acc_ms[c] / args.steps, 4) for c in range(4)},
+                "path_hbm_frac_algorithmic": round(path_bytes * img_per_s / 1e9 / HBM_PEAK_GBS, 4)}
+
+    res = measure(vis, None, 8)
+    dtype = "f32"
+    extra = {}
+    if args.workload == "precision":
+        # FP16 and BF16 storage (per-channel scale), FP32 accumulation; FP16 is the headline
+        forms = {"f32": res}
+        errs = {}
+        sample = [0, w.n_chan // 2]
+        import oracle
+        ref64, _ = oracle.image_batch(vis[:1].cpu().numpy(), w.uvw_m[:1], w.freq_hz, N, w.pixscale, M,
+                                      w.weighting, w.norm, images=sample)
+        blink.image_batch(vis[:1], uvw[:1], freq, grid_n=N, pixscale=w.pixscale, out_n=M,
+                          weighting=w.weighting, norm=w.norm, images=images[:w.n_chan])
+        f32img = images[sample].cpu().double().numpy()
+        errs["f32"] = [float(np.linalg.norm(a - r) / np.linalg.norm(r)) for a, r in zip(f32img, ref64)]
+        for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
+            q, sig = synth.quantize_vis(vis, dt)
+            forms[name] = measure(q, sig, 4)
+            blink.image_batch(q[:1], uvw[:1], freq, grid_n=N, pixscale=w.pixscale, out_n=M,
+                              weighting=w.weighting, norm=w.norm, vis_scale=sig, images=images[:w.n_chan])
+            got = images[sample].cpu().double().numpy()
+            errs[name] = {"rel_l2_vs_fp64_oracle": [float(np.linalg.norm(a - r) / np.linalg.norm(r)) for a, r in zip(got, ref64)],
+                          "rel_l2_vs_fp32_gpu": [float(np.linalg.norm(a - r) / np.linalg.norm(r)) for a, r in zip(got, f32img)],
+                          "peak_abs_err_vs_fp64": [float(np.abs(a - r).max()) for a, r in zip(got, ref64)]}
+            del q
+        res = forms["f16"]
+        dtype = "f16 storage, f32 arithmetic"
+        extra["forms"] = {k: {"images_per_s": round(v["images_per_s"], 1), "ms_per_step": round(v["ms_per_step"], 4),
+                              "kernel_ms_per_step": v["kernel_ms_per_step"], "roofline_frac": v["roofline"]["frac"]}
+                          for k, v in forms.items()}
+        extra["errors_sampled_images"] = errs
+
+    if args.workload == "widefield" and args.plain_loop > 0:
+        # the plain per-image path on the same GPU: one library call per image
+        p1 = blink.blink.make_problem(vis[:1, :1], uvw[:1], freq[:1], N, w.pixscale, M, w.weighting, w.norm)
+        ws1 = blink.workspace(p1, blink.CALL_IMAGE, dev)
+        one = torch.empty((1, M, M), dtype=torch.float32, device=dev)
+        idx = [(i // w.n_chan, i % w.n_chan) for i in range(args.plain_loop)]
+
+        def single(t, c):
+            blink.image_batch(vis[t:t + 1, c:c + 1], uvw[t:t + 1], freq[c:c + 1], grid_n=N, pixscale=w.pixscale,
+                              out_n=M, weighting=w.weighting, norm=w.norm, images=one, ws=ws1)
+        for t, c in idx[:8]:
+            single(t, c)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for t, c in idx:
+            single(t, c)
+        e1.record()
+        torch.cuda.synchronize()
+        extra["plain_per_image_loop"] = {"images_per_s": round(len(idx) / (e0.elapsed_time(e1) / 1e3), 1),
+                                         "images": len(idx), "us_per_image": round(e0.elapsed_time(e1) * 1e3 / len(idx), 2)}
+
+    img_per_s = res["images_per_s"]
+    out = {
+        "metric": METRIC if args.workload == "widefield" else f"dirty images/s ({args.workload})",
+        "value": round(img_per_s, 1), "unit": "images/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": DESCRIPTION[args.workload], "images_per_step": n_img,
+                   "timesteps_per_step": TT, "grid_n": N, "out_n": M, "baselines": B,
+                   "channels": w.n_chan, "chunk_images": args.chunk},
+        "visibilities_per_s": round(img_per_s * unflagged, 1),
+        "nonzero_half_spectrum_columns_mean": round(ncz_mean, 2),
+        "path_hbm_frac_algorithmic": res["path_hbm_frac_algorithmic"],
+        "path_hbm_frac_model_iii": round((unflagged * 8 + H * M * 8 * 2 + M * M * 4) * img_per_s / 1e9 / HBM_PEAK_GBS, 4),
+        "path_hbm_frac_model_i": round((unflagged * 8 + 2 * N * N * 8 + M * M * 4) * img_per_s / 1e9 / HBM_PEAK_GBS, 4),
+        "kernel_ms_per_step": res["kernel_ms_per_step"],
+        "roofline": res["roofline"],
+        "input_generation_s": round(t_gen, 2),
+    }
+    out.update(extra)
+    if args.workload == "plain":
+        out["latency_us_per_image"] = round(res["ms_per_step"] * 1e3, 2)
+
+    sample_n = args.cpu_sample if args.cpu_sample is not None else {"widefield": 128, "plain": 64, "allsky": 4096, "precision": 16}[args.workload]
+    if not args.no_cpu_baseline and sample_n > 0:
+        cores = max(1, min(16, os.cpu_count() or 1))
+        S = min(sample_n, w.n_img)
+        stride = max(1, w.n_chan // S)
+        sample = [(k * stride) % w.n_chan + ((k * stride) // w.n_chan) * w.n_chan for k in range(S)]
+        tmax = max(sample) // w.n_chan + 1
+        vis_cpu = vis[:tmax].cpu().numpy()
+        rate, dt = cpu_baseline(w, vis_cpu, sample, cores)
+        out["cpu_baseline"] = {"value": round(rate, 3), "unit": "images/s", "cores": cores, "kind": "oracle",
+                               "sample": f"{S} images (timesteps < {tmax}, channels every {stride}) of the same "
+                                         f"workload, FP64 numpy oracle, {cores}-process pool, {dt:.1f} s wall"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_diff(args, np, torch, blink, synth, dev):
+    """Forward + backward (hand-written adjoint) of ||I - I_model||^2 w.r.t. vis and gains."""
+    w = synth.widefield(n_time=10, n_chan=32, chan_stride=24)
+    vis0 = synth.visibilities(w, device=dev)
+    uvw = torch.from_numpy(w.uvw_m).to(dev)
+    freq = torch.from_numpy(w.freq_hz).to(dev)
+    gains0 = torch.from_numpy(w.gains).to(dev)
+    a1 = torch.from_numpy(w.ant1).to(dev)
+    a2 = torch.from_numpy(w.ant2).to(dev)
+    rng = np.random.default_rng(20240521 + 4)
+    model = np.zeros((w.n_img, w.out_n, w.out_n), np.float32)
+    for i in range(w.n_img):
+        idx = rng.integers(0, w.out_n, size=(2, 50))
+        model[i, idx[0], idx[1]] = rng.uniform(1, 10, 50)
+    target = torch.from_numpy(model).to(dev)
+
+    def step():
+        vis = vis0.clone().requires_grad_(True)
+        g = gains0.clone().requires_grad_(True)
+        img = blink.blink_image(vis, g, uvw, freq, a1, a2, grid_n=w.grid_n, pixscale=w.pixscale,
+                                out_n=w.out_n, weighting=w.weighting, norm=w.norm)
+        loss = ((img - target) ** 2).sum()
+        loss.backward()
+        return vis.grad, g.grad
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    # forward alone, for the split
+    fw0, fw1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fw0.record()
+    for _ in range(args.steps):
+        blink.image_batch(vis0, uvw, freq, grid_n=w.grid_n, pixscale=w.pixscale, out_n=w.out_n,
+                          weighting=w.weighting, norm=w.norm, gains=gains0, ant1=a1, ant2=a2)
+    fw1.record()
+    torch.cuda.synchronize()
+    fwd_ms = fw0.elapsed_time(fw1) / args.steps
+    out = {"metric": "dirty images/s forward + backward (diff)", "value": round(w.n_img / (ms / 1e3), 1),
+           "unit": "images/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": DESCRIPTION["diff"], "images_per_step": w.n_img, "grid_n": w.grid_n,
+                      "out_n": w.out_n, "baselines": w.n_bl, "antennas": w.n_ant},
+           "forward_ms_per_step": round(fwd_ms, 4), "backward_ms_per_step": round(ms - fwd_ms, 4),
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 # ---------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--timesteps-per-step", type=int, default=10)
-    ap.add_argument("--timesteps", type=int, default=100,
-                    help="timesteps of the job generated into HBM (100 = the whole workload)")
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="widefield",
+                    choices=("widefield", "plain", "allsky", "diff", "precision"))
+    ap.add_argument("--timesteps-per-step", type=int, default=None)
+    ap.add_argument("--timesteps", type=int, default=None,
+                    help="timesteps of the job generated into HBM (default: the whole widefield job)")
     ap.add_argument("--chunk", type=int, default=0, help="images per internal chunk (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=64)
+    ap.add_argument("--cpu-sample", type=int, default=None)
+    ap.add_argument("--plain-loop", type=int, default=256,
+                    help="widefield: also time this many single-image calls (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration for profiling)")
     ap.add_argument("--summarize", metavar="ROCPROF_OUT",
@@ -214,11 +477,14 @@ def main():
     if args.summarize:
         summarize(args.summarize)
         return
-
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "images shard across GPUs with no exchange, see DESIGN.md", file=sys.stderr)
         sys.exit(2)
+    defaults = {"widefield": (20, 3), "plain": (500, 20), "allsky": (3, 1), "diff": (5, 2), "precision": (5, 1)}
+    ds, dw = defaults[args.workload]
+    args.steps = ds if args.steps is None else args.steps
+    args.warmup = dw if args.warmup is None else args.warmup
 
     import numpy as np
     import torch
@@ -235,114 +501,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": a.numel() * 4, "repeats": 5}))
         return
-
     blink.load_library()
-    TT = args.timesteps_per_step
-    w = synth.widefield(n_time=max(TT, args.timesteps), n_chan=768)
-    n_batches = w.n_time // TT
-    t_gen = time.perf_counter()
-    vis = synth.visibilities(w, device=dev)                                # [100][768][8128] c64, 5.0 GB
-    uvw = torch.from_numpy(w.uvw_m).to(dev)
-    freq = torch.from_numpy(w.freq_hz).to(dev)
-    torch.cuda.synchronize()
-    t_gen = time.perf_counter() - t_gen
-
-    n_img = TT * w.n_chan
-    M = w.out_n
-    images = torch.empty((n_img, M, M), dtype=torch.float32, device=dev)   # reused per step
-    p = blink.blink.make_problem(vis[:TT], uvw[:TT], freq, w.grid_n, w.pixscale, M, w.weighting,
-                                 w.norm, None, args.chunk)
-    ws = blink.workspace(p, blink.CALL_IMAGE, dev)
-    times = blink.KernelTimes()
-
-    def step(k, tm=None):
-        b = k % n_batches
-        sl = slice(b * TT, (b + 1) * TT)
-        blink.image_batch(vis[sl], uvw[sl], freq, grid_n=w.grid_n, pixscale=w.pixscale, out_n=M,
-                          weighting=w.weighting, norm=w.norm, chunk_images=args.chunk,
-                          images=images, ws=ws, times=tm)
-
-    for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
-
-    acc_ms = [0.0] * 4
-    acc_n = [0] * 4
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    for k in range(args.steps):
-        step(k, times)
-        for c in range(4):
-            acc_ms[c] += times.ms[c]
-            acc_n[c] += times.launches[c]
-    ev1.record()
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
-    ms_per_step = total_ms / args.steps
-    img_per_s = n_img * args.steps / (total_ms / 1e3)
-    vis_per_s = img_per_s * w.n_bl
-
-    # ---- roofline of the dominant kernel (algorithmic bytes per launch / mean launch time)
-    H, N, B = w.grid_n // 2, w.grid_n, w.n_bl
-    ncz_mean = float(np.mean([nonzero_columns(w, slice((k % n_batches) * TT, (k % n_batches + 1) * TT)).mean()
-                              for k in range(min(args.steps, n_batches))]))
-    per_image = {
-        "grid_cols": B * 8 + ncz_mean * M * 8,     # visibilities in, non-empty half-spectrum columns out
-        "rows": ncz_mean * M * 8 + M * M * 4,      # those columns in, float image cutout out
-    }
-    classes = blink.KCLASS
-    dom = max(range(4), key=lambda c: acc_ms[c])
-    name = classes[dom]
-    imgs_timed = n_img * args.steps
-    mean_ms = acc_ms[dom] / max(acc_n[dom], 1)
-    bytes_per_launch = per_image.get(name, 0) * imgs_timed / max(acc_n[dom], 1)
-    achieved = bytes_per_launch / (mean_ms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("csrc_digest") == _csrc_digest() and tr.get("kernel") == name:
-            traffic = tr.get("hbm_bytes_per_launch")
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": name, "mean_launch_ms": round(mean_ms, 5),
-            "algorithmic_bytes_per_launch": int(bytes_per_launch),
-            "images_per_launch": round(imgs_timed / max(acc_n[dom], 1), 2)}
-    path_bytes = per_image["grid_cols"] + per_image["rows"]
-    kernel_ms = {classes[c]: round(acc_ms[c] / args.steps, 4) for c in range(4)}
-
-    out = {
-        "metric": METRIC, "value": round(img_per_s, 1), "unit": "images/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "widefield 128 tiles (8128 baselines), 768 ch x 100 timesteps, "
-                               "1024^2 grid -> 512^2 cutout, natural weighting",
-                   "images_per_step": n_img, "timesteps_per_step": TT, "grid_n": N, "out_n": M,
-                   "baselines": B, "channels": w.n_chan, "chunk_images": args.chunk},
-        "visibilities_per_s": round(vis_per_s, 1),
-        "nonzero_half_spectrum_columns_mean": round(ncz_mean, 2),
-        "path_hbm_frac_algorithmic": round(path_bytes * img_per_s / 1e9 / HBM_PEAK_GBS, 4),
-        "path_hbm_frac_model_iii": round((B * 8 + H * M * 8 * 2 + M * M * 4) * img_per_s / 1e9 / HBM_PEAK_GBS, 4),
-        "path_hbm_frac_model_i": round((B * 8 + 2 * N * N * 8 + M * M * 4) * img_per_s / 1e9 / HBM_PEAK_GBS, 4),
-        "kernel_ms_per_step": kernel_ms,
-        "roofline": roof,
-        "input_generation_s": round(t_gen, 2),
-    }
-
-    if not args.no_cpu_baseline:
-        cores = max(1, min(16, os.cpu_count() or 1))
-        S = max(1, args.cpu_sample)
-        stride = max(1, w.n_chan // S)
-        sample = [(k * stride) % w.n_chan + (k * stride // w.n_chan) * w.n_chan for k in range(S)]
-        vis_cpu = vis[:2].cpu().numpy()
-        rate, dt = cpu_baseline(w, vis_cpu, sample, cores)
-        out["cpu_baseline"] = {"value": round(rate, 3), "unit": "images/s", "cores": cores,
-                               "kind": "oracle",
-                               "sample": f"{S} images of timestep 0 (channels every {stride}) of "
-                                         f"the same workload, FP64 numpy oracle, {cores}-process "
-                                         f"pool, {dt:.1f} s wall"}
-    print(json.dumps(out), flush=True)
+    if args.workload == "diff":
+        bench_diff(args, np, torch, blink, synth, dev)
+    else:
+        bench_images(args, np, torch, blink, synth, dev)
 
 
 if __name__ == "__main__":

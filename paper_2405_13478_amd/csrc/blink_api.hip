@@ -20,6 +20,7 @@ namespace {
 constexpr int SORT_RUN_SMALL = 1024;
 constexpr int SORT_RUN = 8192;
 constexpr int MAX_GRID_Y = 65535;
+constexpr long long ROWS_WG = 2 * 256;       // resident row-pass workgroups (2 per CU on 256 CUs)
 constexpr size_t CHUNK_TARGET_BYTES = size_t(1) << 30;    // half-spectrum bytes per chunk
 
 bool n_supported(int n) {
@@ -189,10 +190,6 @@ void run_sort(const blink_problem* p, const blink_inputs* in, const Work& w, hip
   Timer none;
   Timer& T_ = tm ? *tm : none;
   const int T = p->n_time, B = p->n_bl;
-  T_.begin(0);
-  hipLaunchKernelGGL(k_sort_init, dim3(cdiv(2LL * T, 256)), dim3(256), 0, st, w.counters, 2 * T);
-  T_.end();
-  if (B == 0 || T == 0) return;
   SortArgs s{};
   s.T = T; s.B = B;
   s.uvw = in->uvw_m; s.flags = in->flags;
@@ -200,18 +197,30 @@ void run_sort(const blink_problem* p, const blink_inputs* in, const Work& w, hip
   s.idx[0] = w.idx[0]; s.idx[1] = w.idx[1];
   s.n_unflagged = w.counters; s.n_valid = w.counters + T;
   s.su = w.su; s.sv = w.sv; s.perm = w.perm;
-  const int run = B <= SORT_RUN_SMALL ? SORT_RUN_SMALL : SORT_RUN;
+  if (B == 0 || B > SORT_RUN) {
+    T_.begin(0);
+    hipLaunchKernelGGL(k_sort_init, dim3(cdiv(2LL * T, 256)), dim3(256), 0, st, w.counters, 2 * T);
+    T_.end();
+  }
+  if (B == 0 || T == 0) return;
   for (int t0 = 0; t0 < T; t0 += MAX_GRID_Y) {
     const int nt = std::min(MAX_GRID_Y, T - t0);
     s.t0 = t0;
     T_.begin(0);
-    if (run == SORT_RUN_SMALL)
-      hipLaunchKernelGGL((k_sort_run<SORT_RUN_SMALL>), dim3(1, nt), dim3(1024), 0, st, s);
-    else
-      hipLaunchKernelGGL((k_sort_run<SORT_RUN>), dim3(cdiv(B, SORT_RUN), nt), dim3(1024), 0, st, s);
+    if (B <= SORT_RUN_SMALL) {
+      hipLaunchKernelGGL((k_sort_small<SORT_RUN_SMALL>), dim3(1, nt), dim3(1024), 0, st, s);
+      T_.end();
+      continue;
+    }
+    if (B <= SORT_RUN) {
+      hipLaunchKernelGGL((k_sort_small<SORT_RUN>), dim3(1, nt), dim3(1024), 0, st, s);
+      T_.end();
+      continue;
+    }
+    hipLaunchKernelGGL((k_sort_run<SORT_RUN>), dim3(cdiv(B, SORT_RUN), nt), dim3(1024), 0, st, s);
     T_.end();
     int src = 0;
-    for (long long wdt = run; wdt < B; wdt *= 2) {
+    for (long long wdt = SORT_RUN; wdt < B; wdt *= 2) {
       T_.begin(0);
       hipLaunchKernelGGL(k_merge, dim3(cdiv(B, 256), nt), dim3(256), 0, st, s, (int)wdt, src);
       T_.end();
@@ -260,7 +269,9 @@ blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t s
     else
       hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, false>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
     T_.end();
-    const dim3 g2(cdiv(p->out_n / 2, Rows<N>::PPW), n);
+    // persistent row pass: two resident workgroups per CU walk the tile list
+    const long long row_tiles = (long long)n * cdiv(p->out_n / 2, Rows<N>::PPW);
+    const dim3 g2((unsigned)std::min<long long>(row_tiles, ROWS_WG));
     T_.begin(3);
     hipLaunchKernelGGL((k_rows<N>), g2, dim3(Rows<N>::THREADS), Rows<N>::LDS, st, a);
     T_.end();
@@ -301,22 +312,29 @@ blink_status adjoint_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t
   for (long long i0 = 0; i0 < n_img; i0 += chunk) {
     const int n = (int)std::min<long long>(chunk, n_img - i0);
     a.img0 = (int)i0; a.nimg = n;
-    const dim3 g1(cdiv(N / 2, Cols<N>::CPW), n);
+    const dim3 gw(cdiv(N / 2, Cols<N>::CPW), n);
     const size_t ldsw = uni ? (size_t)Cols<N>::CPW * N * sizeof(int) : 0;
     if (uni)
-      hipLaunchKernelGGL((k_weights<N, true>), g1, dim3(Cols<N>::THREADS), ldsw, st, a);
+      hipLaunchKernelGGL((k_weights<N, true>), gw, dim3(Cols<N>::THREADS), ldsw, st, a);
     else
-      hipLaunchKernelGGL((k_weights<N, false>), g1, dim3(Cols<N>::THREADS), ldsw, st, a);
+      hipLaunchKernelGGL((k_weights<N, false>), gw, dim3(Cols<N>::THREADS), ldsw, st, a);
     const dim3 g2(cdiv(p->out_n / 2, Rows<N>::PPW), n);
     hipLaunchKernelGGL((k_rows_adj<N>), g2, dim3(Rows<N>::THREADS), Rows<N>::LDS, st, a);
+    // flagged and dropped baselines are never visited: their gradients are zero
     const size_t ng = (size_t)n * a.B;
-    hipLaunchKernelGGL(k_fill2, dim3(cdiv((long long)ng, 256)), dim3(256), 0, st, a.gamma, ng);
+    hipLaunchKernelGGL(k_fill2, dim3(cdiv((long long)ng, 256)), dim3(256), 0, st,
+                       a.vis_grad + (size_t)i0 * a.B, ng);
+    if (a.gains)
+      hipLaunchKernelGGL(k_fill2, dim3(cdiv((long long)ng, 256)), dim3(256), 0, st, a.gamma, ng);
+    a.ntiles = (int)cdiv(N / 2, Cols<N>::CPW);
+    const dim3 g1((unsigned)(cdiv(n, 8) * 8LL * a.ntiles));
     const size_t lds1 = Cols<N>::lds_bytes(uni);
     if (uni)
       hipLaunchKernelGGL((k_cols_adj<N, true>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
     else
       hipLaunchKernelGGL((k_cols_adj<N, false>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
-    hipLaunchKernelGGL(k_adj_finish, dim3(cdiv(a.B, 256)), dim3(256), 0, st, a);
+    if (a.gains)
+      hipLaunchKernelGGL(k_gq_reduce, dim3(cdiv(a.B, 64)), dim3(256), 0, st, a);
   }
   if (a.gains && a.gain_grad)
     hipLaunchKernelGGL(k_gain_grad, dim3(p->n_ant), dim3(256), 0, st, a);

@@ -178,17 +178,32 @@ __host__ __device__ constexpr bool plan_ok(int n) {
 // applies the length-R DFT and writes y[(j / NS) NS R + (j mod NS) + r NS].
 // (Self-sorting radix-R formulation of the Stockham FFT; output in natural
 // order after the last stage.) In place on buf; one wavefront per vector.
+//
+// Padded LDS addresses: when a stride is a multiple of 16 the padded index of
+// base + r * stride is pad(base) + r * (stride + stride / 16), and for NS = 1
+// with R dividing 16 it is pad(j R) + r, so every access is a per-lane base
+// plus a compile-time offset that folds into the LDS instruction.
 template <int N, int R, int NS, int SIGN>
 __device__ __forceinline__ void stockham_stage(float2* buf, int lane, const float2* __restrict__ tw) {
   constexpr int NB = N / R;
   constexpr int PER = (NB + WAVE - 1) / WAVE;
+  constexpr bool RD_LIN = NB % 16 == 0;                       // read offsets fold
+  constexpr bool WR_LIN = NS % 16 == 0 || (NS == 1 && 16 % R == 0);   // write offsets fold
+  constexpr int RD_STEP = NB + NB / 16;
+  constexpr int WR_STEP = NS == 1 ? 1 : NS + NS / 16;
   float2 v[PER][R];
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
     const int j = lane + p * WAVE;
     if (NB % WAVE == 0 || j < NB) {
+      if constexpr (RD_LIN) {
+        const int b = pad(j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[p][r] = buf[pad(j + r * NB)];
+        for (int r = 0; r < R; ++r) v[p][r] = buf[b + r * RD_STEP];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[p][r] = buf[pad(j + r * NB)];
+      }
     }
   }
   wave_sync();
@@ -199,17 +214,24 @@ __device__ __forceinline__ void stockham_stage(float2* buf, int lane, const floa
       const int k = j % NS;
       if constexpr (NS > 1) {
         constexpr int STEP = N / (NS * R);
+        const float2* t1 = tw + k * STEP;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 w = tw[k * r * STEP];
+          float2 w = t1[(r - 1) * k * STEP];
           if (SIGN < 0) w.y = -w.y;
           v[p][r] = cmul(v[p][r], w);
         }
       }
       dft<R, SIGN>(v[p]);
       const int base = (j / NS) * NS * R + k;
+      if constexpr (WR_LIN) {
+        const int b = pad(base);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[pad(base + r * NS)] = v[p][r];
+        for (int r = 0; r < R; ++r) buf[b + r * WR_STEP] = v[p][r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[pad(base + r * NS)] = v[p][r];
+      }
     }
   }
   wave_sync();

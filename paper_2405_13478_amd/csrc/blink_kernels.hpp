@@ -124,6 +124,65 @@ __global__ void __launch_bounds__(1024) k_sort_run(SortArgs a) {
   if (threadIdx.x == 0 && s_unf) atomicAdd(&a.n_unflagged[t], s_unf);
 }
 
+// Whole per-timestep order in one kernel when B <= RUN: load, bitonic sort in
+// LDS, then the sorted u, v, baseline index and the two counters of the
+// timestep (one workgroup per timestep, so no atomics and no initialisation).
+template <int RUN>
+__global__ void __launch_bounds__(1024) k_sort_small(SortArgs a) {
+  __shared__ unsigned long long sk[RUN];
+  __shared__ int si[RUN];
+  __shared__ int s_unf, s_val;
+  const int t = a.t0 + blockIdx.y;
+  const size_t tb = (size_t)t * a.B;
+  if (threadIdx.x == 0) { s_unf = 0; s_val = 0; }
+  __syncthreads();
+  int unf = 0, val = 0;
+  for (int i = threadIdx.x; i < RUN; i += blockDim.x) {
+    unsigned long long k = KEY_MAX;
+    int id = 0x7fffffff;
+    if (i < a.B) {
+      const double u = a.uvw[(tb + i) * 3 + 0];
+      const double v = a.uvw[(tb + i) * 3 + 1];
+      const bool flagged = a.flags != nullptr && a.flags[tb + i] != 0;
+      unf += flagged ? 0 : 1;
+      if (!flagged && isfinite(u) && isfinite(v)) { k = order_key(u); ++val; }
+      id = i;
+    }
+    sk[i] = k;
+    si[i] = id;
+  }
+  if (unf) atomicAdd(&s_unf, unf);
+  if (val) atomicAdd(&s_val, val);
+  __syncthreads();
+  for (int k = 2; k <= RUN; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < RUN / 2; i += blockDim.x) {
+        const int lo = 2 * i - (i & (j - 1));
+        const int hi = lo + j;
+        const bool up = (lo & k) == 0;
+        const unsigned long long ka = sk[lo], kb = sk[hi];
+        const int ia = si[lo], ib = si[hi];
+        const bool gt = ka > kb || (ka == kb && ia > ib);
+        if (gt == up) {
+          sk[lo] = kb; sk[hi] = ka;
+          si[lo] = ib; si[hi] = ia;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int j = threadIdx.x; j < a.B; j += blockDim.x) {
+    const int b = si[j];
+    a.su[tb + j] = a.uvw[(tb + b) * 3 + 0];
+    a.sv[tb + j] = a.uvw[(tb + b) * 3 + 1];
+    a.perm[tb + j] = b;
+  }
+  if (threadIdx.x == 0) {
+    a.n_unflagged[t] = s_unf;
+    a.n_valid[t] = s_val;
+  }
+}
+
 // Merge neighbouring sorted runs of width w: each element's output position
 // is its rank in its own run plus the number of smaller elements in the other
 // run (binary search). All (key, index) pairs are distinct.
@@ -274,10 +333,14 @@ __device__ __forceinline__ float2 load_vis(const ImgArgs& a, size_t off, int b, 
 
 // Grid the column's entries: sorted positions [dlo, dhi) add V' at row i_v,
 // positions [clo, chi) (the mirror column) add conj(V') at row -i_v. Both
-// ranges are walked as one list, 64 entries per step, so each step issues its
-// loads together. Only this wavefront touches the column, so the LDS adds
-// happen in a fixed order (steps in sequence, lanes in LDS order within a
-// step). Returns the kept direct and conjugate entries.
+// ranges are walked as one list, GU x 64 entries per step: every step first
+// issues the sorted-list loads of all its entries, then their visibility
+// gathers, then the LDS adds, so a wavefront keeps GU times more loads in
+// flight. Only this wavefront touches the column, so the LDS adds happen in a
+// fixed order (steps in sequence; within a step, sub-steps in sequence and
+// lanes in LDS order). Returns the kept direct and conjugate entries.
+constexpr int GU = 4;
+
 template <int N, bool COUNT>
 __device__ __forceinline__ int2 grid_points(const ImgArgs& a, float2* buf, int* cnt, int dlo, int dhi,
                                             int clo, int chi, int t, int ch, double s, int lane) {
@@ -286,33 +349,43 @@ __device__ __forceinline__ int2 grid_points(const ImgArgs& a, float2* buf, int* 
   const int nd = dhi - dlo;
   const int total = nd + (chi - clo);
   int kd = 0, kc = 0;
-  for (int i0 = 0; i0 < total; i0 += WAVE) {
-    const int i = i0 + lane;
-    bool ok = i < total;
-    const bool conj = i >= nd;
-    int row = 0;
-    float2 val = make_float2(0.f, 0.f);
-    if (ok) {
-      const int j = conj ? clo + (i - nd) : dlo + i;
-      const double iv = rint(a.sv[tb + j] * s);
-      const int b = a.perm[tb + j];
-      ok = fabs(iv) < (double)(N / 2);
-      if (ok) {
-        int r = (int)iv;
-        if (conj) r = -r;
-        row = r < 0 ? r + N : r;
-        val = load_vis(a, vb + b, b, ch);
-        if (conj) val.y = -val.y;
+  for (int i0 = 0; i0 < total; i0 += GU * WAVE) {
+    double sv[GU];
+    int bl[GU];
+    bool ok[GU], cj[GU];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int i = i0 + u * WAVE + lane;
+      ok[u] = i < total;
+      cj[u] = i >= nd;
+      const int j = cj[u] ? clo + (i - nd) : dlo + i;
+      sv[u] = ok[u] ? a.sv[tb + j] : 0.0;
+      bl[u] = ok[u] ? a.perm[tb + j] : 0;
+    }
+    int row[GU];
+    float2 val[GU];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const double iv = rint(sv[u] * s);
+      ok[u] = ok[u] && fabs(iv) < (double)(N / 2);
+      int r = (int)iv;
+      if (cj[u]) r = -r;
+      row[u] = r < 0 ? r + N : r;
+      val[u] = ok[u] ? load_vis(a, vb + bl[u], bl[u], ch) : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      if (ok[u]) {
+        float2 v = val[u];
+        if (cj[u]) v.y = -v.y;
+        float2* p = &buf[pad(row[u])];
+        atomicAdd(&p->x, v.x);
+        atomicAdd(&p->y, v.y);
+        if (COUNT) atomicAdd(&cnt[row[u]], 1);
       }
+      kd += __popcll(__ballot(ok[u] && !cj[u]));
+      kc += __popcll(__ballot(ok[u] && cj[u]));
     }
-    if (ok) {
-      float2* p = &buf[pad(row)];
-      atomicAdd(&p->x, val.x);
-      atomicAdd(&p->y, val.y);
-      if (COUNT) atomicAdd(&cnt[row], 1);
-    }
-    kd += __popcll(__ballot(ok && !conj));
-    kc += __popcll(__ballot(ok && conj));
   }
   return make_int2(kd, kc);
 }
@@ -355,7 +428,8 @@ struct Cols {
 // (workgroup L runs on XCD L mod 8): the image's visibility row and the
 // timestep's sorted lists are then fetched into a single L2.
 template <int N, int MODE, bool UNI>
-__global__ void __launch_bounds__(Cols<N>::THREADS) k_grid_cols(ImgArgs a) {
+__global__ void __launch_bounds__(Cols<N>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+k_grid_cols(ImgArgs a) {
   extern __shared__ float4 lds_raw[];
   __shared__ int red[2 * Cols<N>::CPW];
   constexpr int H = N / 2;
@@ -489,31 +563,60 @@ struct Rows {
 // (A_full[N/2] = 0: the Nyquist column is never gridded), so one complex
 // transform yields row m as Re z and row m+1 as Im z. The shift, 1/W and the
 // cutout are applied as the rows are stored.
+// Persistent form: a fixed grid of workgroups walks the (image, row tile)
+// list. For N <= 1024, while the transforms of one tile run, the
+// half-spectrum slice of the next tile is already in flight into registers,
+// so the HBM latency of the loads hides behind the arithmetic of the previous
+// tile (larger N would need too many registers and loads per tile instead).
 template <int N>
 __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
   extern __shared__ float4 lds_raw[];
   constexpr int H = N / 2;
   constexpr int PPW = Rows<N>::PPW;
   constexpr int ST = Rows<N>::STRIDE;
+  constexpr int THR = Rows<N>::THREADS;
+  constexpr int EPT = (H * PPW + THR - 1) / THR;     // half-spectrum float4 loads per thread
+  constexpr bool PREF = EPT <= 8;
+  constexpr int NPRE = PREF ? EPT : 1;
   float2* lds = reinterpret_cast<float2*>(lds_raw);
   const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-  const int li = blockIdx.y;
-  const int img = a.img0 + li;
   const int M = a.M;
   const int npair = M / 2;
-  const int p0 = blockIdx.x * PPW;            // first row pair of this workgroup
-  const int nz = min(H, a.ncz[img]);          // columns >= nz of the half spectrum are zero
-  const int W = sum_partials(a.wpart, img, a.wstride, a.wtiles, lane);
-  const float scale = a.norm ? (W > 0 ? 1.0f / (float)W : 0.0f) : 1.0f;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && a.weight_sum) a.weight_sum[img] = (float)W;
+  const int ntr = (npair + PPW - 1) / PPW;           // row tiles per image
+  const int total = a.nimg * ntr;
   const float2* tw = stage_twiddles<N>(lds + PPW * ST);
 
-  const float4* src = reinterpret_cast<const float4*>(a.half + (size_t)li * H * M);
-  for (int e = threadIdx.x; e < H * PPW; e += blockDim.x) {
-    const int k = e / PPW, p = e % PPW;
-    if (p0 + p < npair) {
-      const float4 ab = k < nz ? src[((size_t)k * M + 2 * (p0 + p)) / 2] : make_float4(0.f, 0.f, 0.f, 0.f);
-      float2* z = lds + p * ST;
+  // thread t always serves pair slot t % PPW and columns t / PPW + i * (THR / PPW)
+  const int kt = threadIdx.x / PPW, pt = threadIdx.x % PPW;
+  auto load = [&](int tile, int i) -> float4 {
+    const int li = tile / ntr, p0 = (tile % ntr) * PPW;
+    const int nz = min(H, a.ncz[a.img0 + li]);
+    const int k = kt + i * (THR / PPW);
+    const float4* src = reinterpret_cast<const float4*>(a.half + (size_t)li * H * M) + (p0 + pt);
+    return (k < nz && p0 + pt < npair) ? src[(size_t)k * (M / 2)] : make_float4(0.f, 0.f, 0.f, 0.f);
+  };
+  float4 pre[NPRE];
+  int tile = blockIdx.x;
+  if (PREF && tile < total) {
+#pragma unroll
+    for (int i = 0; i < NPRE; ++i) pre[i] = load(tile, i);
+  }
+#pragma nounroll
+  for (; tile < total; tile += gridDim.x) {
+    // lane-dependent addresses are recomputed inside the loop: hoisted out of
+    // it they would stay live across the transforms and cost occupancy
+    int lane_i = lane, ln = threadIdx.x;
+    asm volatile("" : "+v"(lane_i), "+v"(ln));
+    const int li = tile / ntr, p0 = (tile % ntr) * PPW;
+    const int img = a.img0 + li;
+    const int W = sum_partials(a.wpart, img, a.wstride, a.wtiles, lane_i);
+    const float scale = a.norm ? (W > 0 ? 1.0f / (float)W : 0.0f) : 1.0f;
+    if (p0 == 0 && ln == 0 && a.weight_sum) a.weight_sum[img] = (float)W;
+    const int kti = ln / PPW, pti = ln % PPW;
+    __syncthreads();                                  // previous tile's rows have left LDS
+    auto put = [&](int i, float4 ab) {
+      const int k = kti + i * (THR / PPW);
+      float2* z = lds + pti * ST;
       if (k == 0) {
         z[pad(0)] = make_float2(ab.x, ab.z);
         z[pad(H)] = make_float2(0.f, 0.f);
@@ -521,21 +624,33 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
         z[pad(k)] = make_float2(ab.x - ab.w, ab.y + ab.z);
         z[pad(N - k)] = make_float2(ab.x + ab.w, ab.z - ab.y);
       }
+    };
+    if constexpr (PREF) {
+#pragma unroll
+      for (int i = 0; i < NPRE; ++i)
+        if (kti + i * (THR / PPW) < H) put(i, pre[i]);
+    } else {
+      for (int i = 0; kti + i * (THR / PPW) < H; ++i) put(i, load(tile, i));
     }
-  }
-  __syncthreads();
-  const int pair = p0 + wave;
-  if (pair >= npair) return;
-  float2* z = lds + wave * ST;
-  wave_fft<N, +1>(z, lane, tw);
-  float* r0 = a.images + ((size_t)img * M + 2 * pair) * M;
-  float* r1 = r0 + M;
-  for (int l = lane; l < M; l += WAVE) {
-    int q = l - M / 2;
-    q = q < 0 ? q + N : q;
-    const float2 v = z[pad(q)];
-    r0[l] = v.x * scale;
-    r1[l] = v.y * scale;
+    __syncthreads();
+    if (PREF && tile + (int)gridDim.x < total) {
+#pragma unroll
+      for (int i = 0; i < NPRE; ++i) pre[i] = load(tile + gridDim.x, i);
+    }
+    const int pair = p0 + wave;
+    if (pair < npair) {
+      float2* z = lds + wave * ST;
+      wave_fft<N, +1>(z, lane_i, tw);
+      float* r0 = a.images + ((size_t)img * M + 2 * pair) * M;
+      float* r1 = r0 + M;
+      for (int l = lane_i; l < M; l += WAVE) {
+        int q = l - M / 2;
+        q = q < 0 ? q + N : q;
+        const float2 v = z[pad(q)];
+        r0[l] = v.x * scale;
+        r1[l] = v.y * scale;
+      }
+    }
   }
 }
 
@@ -600,7 +715,7 @@ __global__ void __launch_bounds__(Cols<N>::THREADS) k_weights(ImgArgs a) {
   const int t = img / a.C, ch = img - t * a.C;
   const int cs = blockIdx.x * CPW + wave;
   int w = 0;
-  if (cs < H) {
+  if (cs < min(H, a.ncz[img])) {
     int* cnt = lw_raw + wave * N;
     const double s = cells_per_metre(a.freq[ch], a.ndx);
     if (UNI) {
@@ -648,6 +763,7 @@ __global__ void __launch_bounds__(Cols<N>::THREADS) k_weights(ImgArgs a) {
 // times 1/W, shift undone) packed as z = a + i b, forward transform, then the
 // half-spectrum gradients c_k A[k], c_k B[k] (c_0 = 1, c_k = 2) with
 // A[k] = (Z[k] + conj Z[N-k]) / 2 and B[k] = (Z[k] - conj Z[N-k]) / (2i).
+// Only the columns that can hold baselines (k < ncz) are stored.
 template <int N>
 __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows_adj(ImgArgs a) {
   extern __shared__ float4 lds_raw[];
@@ -661,8 +777,11 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows_adj(ImgArgs a) {
   const int M = a.M;
   const int npair = M / 2;
   const int p0 = blockIdx.x * PPW;
+  const int nz = min(H, a.ncz[img]);
   const int W = sum_partials(a.wpart, img, a.wstride, a.wtiles, lane);
   const float scale = a.norm ? (W > 0 ? 1.0f / (float)W : 0.0f) : 1.0f;
+  const float2* tw = stage_twiddles<N>(lds + PPW * ST);
+  __syncthreads();
   const int pair = p0 + wave;
   if (pair < npair) {
     float2* z = lds + wave * ST;
@@ -676,11 +795,11 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows_adj(ImgArgs a) {
       z[pad(q)] = make_float2(g0[l] * scale, g1[l] * scale);
     }
     wave_sync();
-    wave_fft<N, -1>(z, lane, TwTable<N>::get());
+    wave_fft<N, -1>(z, lane, tw);
   }
   __syncthreads();
   float4* dst = reinterpret_cast<float4*>(a.half + (size_t)li * H * M);
-  for (int e = threadIdx.x; e < H * PPW; e += blockDim.x) {
+  for (int e = threadIdx.x; e < nz * PPW; e += blockDim.x) {
     const int k = e / PPW, p = e % PPW;
     if (p0 + p < npair) {
       const float2* z = lds + p * ST;
@@ -699,24 +818,38 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows_adj(ImgArgs a) {
 
 // Adjoint of k_grid_cols (MODE_IMAGE): column gradient at the cutout rows,
 // forward transform along v, cell weight, then gather (degrid) at every
-// entry of the column: gamma'_b += w G[i_v] (direct) or conj(w G[-i_v]).
+// entry of the column: gamma'_b = w G[i_v] (direct) or conj(w G[-i_v])
+// (mirror column), both for i_u = 0. Writes vis_grad = conj(g1 conj g2) gamma'
+// and, with gains, gq = gamma' conj(V) for the gain gradient. Same XCD-grouped
+// 1D layout and empty-column skip as the forward kernel.
 template <int N, bool UNI>
 __global__ void __launch_bounds__(Cols<N>::THREADS) k_cols_adj(ImgArgs a) {
   extern __shared__ float4 lds_raw[];
   constexpr int H = N / 2;
   constexpr int CPW = Cols<N>::CPW;
-  float2* lds = reinterpret_cast<float2*>(lds_raw);
-  int* lcnt = reinterpret_cast<int*>(lds + CPW * Cols<N>::STRIDE);
-  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-  const int li = blockIdx.y;
+  const int L = blockIdx.x;
+  const int r8 = L >> 3;
+  const int li = (r8 / a.ntiles) * 8 + (L & 7);
+  const int tile = r8 % a.ntiles;
+  if (li >= a.nimg) return;
   const int img = a.img0 + li;
+  const int nz = min(H, a.ncz[img]);
+  const int c0 = tile * CPW;
+  if (c0 >= nz) return;                               // no baseline lives in this tile
+  float2* lds = reinterpret_cast<float2*>(lds_raw);
+  float2* ltw = lds + CPW * Cols<N>::STRIDE;
+  int* lcnt = reinterpret_cast<int*>(ltw + Cols<N>::TW);
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   const int t = img / a.C, ch = img - t * a.C;
-  const int cs = blockIdx.x * CPW + wave;
-  if (cs >= H) return;
+  const int cs = c0 + wave;
+  const bool active = cs < nz;
   float2* buf = lds + wave * Cols<N>::STRIDE;
   int* cnt = UNI ? lcnt + wave * N : nullptr;
   const double s = cells_per_metre(a.freq[ch], a.ndx);
   const int M = a.M;
+  const float2* tw = stage_twiddles<N>(ltw);
+  __syncthreads();
+  if (!active) return;
   for (int r = lane; r < Cols<N>::STRIDE; r += WAVE) buf[r] = make_float2(0.f, 0.f);
   if (UNI)
     for (int r = lane; r < N; r += WAVE) cnt[r] = 0;
@@ -745,8 +878,8 @@ __global__ void __launch_bounds__(Cols<N>::THREADS) k_cols_adj(ImgArgs a) {
     }
   }
   wave_sync();
-  wave_fft<N, -1>(buf, lane, TwTable<N>::get());
-  float2* gam = a.gamma + (size_t)li * a.B;
+  wave_fft<N, -1>(buf, lane, tw);
+  const size_t vb = (size_t)img * a.B;
   // direct entries (and, for column 0, the conjugate entry of the same baseline)
   for (int pass = 0; pass < (cs == 0 ? 1 : 2); ++pass) {
     const int lo = pass ? clo : dlo, hi = pass ? chi : dhi;
@@ -756,7 +889,7 @@ __global__ void __launch_bounds__(Cols<N>::THREADS) k_cols_adj(ImgArgs a) {
         const int r = (int)iv;
         const int rp = r < 0 ? r + N : r;
         const int rm = -r < 0 ? -r + N : -r;
-        float2 g = make_float2(0.f, 0.f);
+        float2 g;
         if (pass == 0) {
           float2 v = buf[pad(rp)];
           if (UNI) v = cscale(v, 1.0f / (float)cnt[rp]);
@@ -771,7 +904,14 @@ __global__ void __launch_bounds__(Cols<N>::THREADS) k_cols_adj(ImgArgs a) {
           if (UNI) w = cscale(w, 1.0f / (float)cnt[rm]);
           g = cconj(w);
         }
-        gam[a.perm[tb + j]] = g;
+        const int b = a.perm[tb + j];
+        if (a.gains) {
+          a.vis_grad[vb + b] = cmul(cconj(baseline_gain(a, b)), g);
+          const float2 v = static_cast<const float2*>(a.vis)[vb + b];
+          a.gamma[(size_t)li * a.B + b] = cmul(g, cconj(v));
+        } else {
+          a.vis_grad[vb + b] = g;
+        }
       }
     }
   }
@@ -782,24 +922,19 @@ __global__ void k_fill2(float2* p, size_t n) {
   if (i < n) p[i] = make_float2(0.f, 0.f);
 }
 
-// vis_grad = conj(g1) g2 gamma' and, per baseline, pacc += sum over this
-// chunk's images of gamma' conj(V) (images taken in order: deterministic).
-__global__ void __launch_bounds__(256) k_adj_finish(ImgArgs a) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= a.B) return;
-  float2 gb = make_float2(1.f, 0.f);
-  if (a.gains) gb = cconj(baseline_gain(a, b));
+// pacc[b] += sum over this chunk's images of gq[li][b]: 64 baselines per
+// workgroup, 4 image slices per baseline, slices combined in a fixed order.
+__global__ void __launch_bounds__(256) k_gq_reduce(ImgArgs a) {
+  __shared__ float2 part[4][64];
+  const int bl = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int b = blockIdx.x * 64 + bl;
   float2 acc = make_float2(0.f, 0.f);
-  for (int li = 0; li < a.nimg; ++li) {
-    const int img = a.img0 + li;
-    const float2 g = a.gamma[(size_t)li * a.B + b];
-    a.vis_grad[(size_t)img * a.B + b] = a.gains ? cmul(gb, g) : g;
-    if (a.gains) {
-      const float2 v = static_cast<const float2*>(a.vis)[(size_t)img * a.B + b];
-      acc = cadd(acc, cmul(g, cconj(v)));
-    }
-  }
-  if (a.gains) a.pacc[b] = cadd(a.pacc[b], acc);
+  if (b < a.B)
+    for (int li = sl; li < a.nimg; li += 4) acc = cadd(acc, a.gamma[(size_t)li * a.B + b]);
+  part[sl][bl] = acc;
+  __syncthreads();
+  if (sl == 0 && b < a.B)
+    a.pacc[b] = cadd(a.pacc[b], cadd(cadd(part[0][bl], part[1][bl]), cadd(part[2][bl], part[3][bl])));
 }
 
 // gain_grad[a] = sum_{b: a1 = a} g2 p_b + sum_{b: a2 = a} g1 conj(p_b)
