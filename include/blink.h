@@ -66,9 +66,10 @@ typedef struct { float re, im; } blink_c32;
 
 typedef enum {
   BLINK_OK = 0,
-  BLINK_E_ARG = -1,          /* null required pointer, bad enum, non-finite or <= 0 pixscale */
+  BLINK_E_ARG = -1,          /* null required pointer, bad enum or tunable, non-finite or <= 0 pixscale */
   BLINK_E_SIZE = -2,         /* negative sizes, odd N or M, M > N, element count overflow   */
-  BLINK_E_UNSUPPORTED = -3,  /* N without a compiled transform plan, or a combination not built */
+  BLINK_E_UNSUPPORTED = -3,  /* N without a compiled transform plan, a combination not built,
+                                or a tile width whose workgroup does not fit in LDS            */
   BLINK_E_WORKSPACE = -4,    /* workspace null, misaligned or smaller than required          */
   BLINK_E_HIP = -5           /* a HIP launch failed (hipGetLastError after the enqueue)       */
 } blink_status;
@@ -94,6 +95,10 @@ typedef struct {
   int32_t norm;          /* blink_norm                                                */
   int32_t vis_type;      /* blink_vis_type                                            */
   int32_t chunk_images;  /* images per internal chunk; 0 = library default            */
+  int32_t cols_per_wg;   /* u-cell columns per workgroup of the image path's column    */
+                         /* kernel: 0 = library default, else 2, 4 or 8                */
+  int32_t rows_wg;       /* row pass: 0 = one workgroup per row tile, > 0 = that many  */
+                         /* persistent workgroups walking the row tiles                */
 } blink_problem;
 
 typedef struct {          /* device pointers; the optional ones may be NULL            */

@@ -41,7 +41,8 @@ class Problem(ctypes.Structure):
                 ("n_ant", ctypes.c_int32), ("grid_n", ctypes.c_int32), ("out_n", ctypes.c_int32),
                 ("pixscale", ctypes.c_double), ("weighting", ctypes.c_int32),
                 ("norm", ctypes.c_int32), ("vis_type", ctypes.c_int32),
-                ("chunk_images", ctypes.c_int32)]
+                ("chunk_images", ctypes.c_int32), ("cols_per_wg", ctypes.c_int32),
+                ("rows_wg", ctypes.c_int32)]
 
 
 class Inputs(ctypes.Structure):
@@ -130,7 +131,7 @@ def _check(code, what):
 
 
 def make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n=None, weighting=NATURAL,
-                 norm=NORM_WEIGHTS, gains=None, chunk_images=0) -> Problem:
+                 norm=NORM_WEIGHTS, gains=None, chunk_images=0, cols_per_wg=0, rows_wg=0) -> Problem:
     if vis.dtype == torch.complex64:
         T, C, B = vis.shape
         vt = VIS_C64
@@ -144,7 +145,8 @@ def make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n=None, weighting=NA
     return Problem(n_time=T, n_chan=C, n_bl=B, n_ant=0 if gains is None else gains.shape[0],
                    grid_n=grid_n, out_n=grid_n if out_n is None else out_n,
                    pixscale=float(pixscale), weighting=int(weighting), norm=int(norm),
-                   vis_type=vt, chunk_images=int(chunk_images))
+                   vis_type=vt, chunk_images=int(chunk_images), cols_per_wg=int(cols_per_wg),
+                   rows_wg=int(rows_wg))
 
 
 def make_inputs(p: Problem, vis, uvw_m, freq_hz, flags=None, vis_scale=None, ant1=None,
@@ -172,16 +174,34 @@ def workspace(p: Problem, call: int, device) -> torch.Tensor:
 
 
 # ---------------------------------------------------------------- calls
+def tuning_for(grid_n, out_n, n_bl, weighting, vis_type, chunk_images=None, cols_per_wg=None,
+               rows_wg=None):
+    """Tunables for a shape: explicit values win, then the autotuner's cache, then 0 (defaults)."""
+    from . import autotune
+    t = autotune.lookup(grid_n, out_n, n_bl, weighting, vis_type) or {}
+    pick = lambda v, k: int(v) if v is not None else int(t.get(k, 0))
+    return dict(chunk_images=pick(chunk_images, "chunk_images"), cols_per_wg=pick(cols_per_wg, "cols_per_wg"),
+                rows_wg=pick(rows_wg, "rows_wg"))
+
+
+def _vis_type(vis):
+    return {torch.complex64: VIS_C64, torch.float16: VIS_F16, torch.bfloat16: VIS_BF16}.get(vis.dtype, -1)
+
+
 def image_batch(vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None, weighting=NATURAL,
                 norm=NORM_WEIGHTS, flags=None, vis_scale=None, ant1=None, ant2=None, gains=None,
-                chunk_images=0, images=None, weight_sum=None, ws=None, stream=None, times=None):
+                chunk_images=None, cols_per_wg=None, rows_wg=None, images=None, weight_sum=None,
+                ws=None, stream=None, times=None):
     """Dirty images [T*C][M][M] float32 of the cube (blink_image_batch).
 
+    Tunables left as None come from the autotuner's cache for this shape.
     With ``times`` (a KernelTimes) the instrumented twin blink_image_batch_timed
     runs instead: same results, per-kernel-class event timings, host waits.
     """
     lib = load_library()
-    p = make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, weighting, norm, gains, chunk_images)
+    M = grid_n if out_n is None else out_n
+    tun = tuning_for(grid_n, M, vis.shape[2], weighting, _vis_type(vis), chunk_images, cols_per_wg, rows_wg)
+    p = make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, weighting, norm, gains, **tun)
     inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains)
     n_img, M = p.n_time * p.n_chan, p.out_n
     if images is None:

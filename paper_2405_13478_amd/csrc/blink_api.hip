@@ -20,7 +20,6 @@ namespace {
 constexpr int SORT_RUN_SMALL = 1024;
 constexpr int SORT_RUN = 8192;
 constexpr int MAX_GRID_Y = 65535;
-constexpr long long ROWS_WG = 2 * 256;       // resident row-pass workgroups (2 per CU on 256 CUs)
 constexpr size_t CHUNK_TARGET_BYTES = size_t(1) << 30;    // half-spectrum bytes per chunk
 
 bool n_supported(int n) {
@@ -83,7 +82,7 @@ size_t carve(const blink_problem* p, int call, int chunk, char* base, Work* w) {
   const size_t n_img = (size_t)p->n_time * (size_t)p->n_chan;
   x.bnd = (int*)take(n_img * (N + 2) * 4);
   x.ncz = (int*)take(n_img * 4);
-  x.wstride = (int)((N + cols_per_wg((int)N) - 1) / cols_per_wg((int)N));
+  x.wstride = (int)((N + 1) / 2);      // column tiles per image for any tile width >= 2
   x.wpart = (int*)take(n_img * x.wstride * 4);
   x.kpart = (int*)take(n_img * x.wstride * 4);
   if (call == BLINK_CALL_IMAGE || call == BLINK_CALL_ADJOINT)
@@ -104,6 +103,9 @@ blink_status validate_problem(const blink_problem* p, int call) {
   if (p->norm != BLINK_NORM_NONE && p->norm != BLINK_NORM_WEIGHTS) return BLINK_E_ARG;
   if (p->vis_type < BLINK_VIS_C64 || p->vis_type > BLINK_VIS_BF16) return BLINK_E_ARG;
   if (p->chunk_images < 0) return BLINK_E_ARG;
+  if (p->cols_per_wg != 0 && p->cols_per_wg != 2 && p->cols_per_wg != 4 && p->cols_per_wg != 8)
+    return BLINK_E_ARG;
+  if (p->rows_wg < 0) return BLINK_E_ARG;
   if (call < BLINK_CALL_GRID || call > BLINK_CALL_ADJOINT) return BLINK_E_ARG;
   if (p->grid_n < 2 || (p->grid_n & 1)) return BLINK_E_SIZE;
   if (call != BLINK_CALL_GRID) {
@@ -248,32 +250,53 @@ ImgArgs make_args(const blink_problem* p, const blink_inputs* in, const Work& w)
   return a;
 }
 
+template <int N, bool UNI, int CPW>
+void launch_cols_image(ImgArgs& a, int n, hipStream_t st) {
+  using C_ = Cols<N, CPW>;
+  a.wtiles = a.ntiles = (int)cdiv(N / 2, CPW);
+  const dim3 g1((unsigned)(cdiv(n, 8) * 8LL * a.ntiles));
+  hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, UNI, CPW>), g1, dim3(C_::THREADS), C_::lds_bytes(UNI), st, a);
+}
+
+template <int N, bool UNI>
+void launch_cols_image(ImgArgs& a, int n, int cpw, hipStream_t st) {
+  if (cpw == 2) launch_cols_image<N, UNI, 2>(a, n, st);
+  else if (cpw == 4) launch_cols_image<N, UNI, 4>(a, n, st);
+  else launch_cols_image<N, UNI, 8>(a, n, st);
+}
+
+// LDS one workgroup of the column kernel needs at a tile width (checked
+// against the 160 KiB of a gfx950 CU before any launch).
+template <int N>
+size_t cols_lds(int cpw, bool uni) {
+  return cpw == 2 ? Cols<N, 2>::lds_bytes(uni) : cpw == 4 ? Cols<N, 4>::lds_bytes(uni)
+                                                          : Cols<N, 8>::lds_bytes(uni);
+}
+constexpr size_t LDS_PER_CU = size_t(160) << 10;
+
 template <int N>
 blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t st, Timer* tm) {
   Timer& T_ = *tm;
   const long long n_img = (long long)p->n_time * p->n_chan;
   const bool uni = p->weighting == BLINK_UNIFORM;
-  const size_t lds1 = Cols<N>::lds_bytes(uni);
-  a.wtiles = (int)cdiv(N / 2, Cols<N>::CPW);
+  const int cpw = p->cols_per_wg ? p->cols_per_wg : cols_per_wg(N);
+  if (cols_lds<N>(cpw, uni) > LDS_PER_CU) return BLINK_E_UNSUPPORTED;
+  a.wtiles = (int)cdiv(N / 2, cpw);
   T_.begin(1);
   hipLaunchKernelGGL(k_bounds, dim3((unsigned)n_img), dim3(256), 0, st, a);
   T_.end();
   for (long long i0 = 0; i0 < n_img; i0 += chunk) {
     const int n = (int)std::min<long long>(chunk, n_img - i0);
     a.img0 = (int)i0; a.nimg = n;
-    a.ntiles = (int)cdiv(N / 2, Cols<N>::CPW);
-    const dim3 g1((unsigned)(cdiv(n, 8) * 8LL * a.ntiles));
     T_.begin(2);
-    if (uni)
-      hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, true>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
-    else
-      hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, false>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
+    if (uni) launch_cols_image<N, true>(a, n, cpw, st);
+    else launch_cols_image<N, false>(a, n, cpw, st);
     T_.end();
-    // persistent row pass: two resident workgroups per CU walk the tile list
+    // row pass: one workgroup per row tile, or a persistent grid of rows_wg workgroups
     const long long row_tiles = (long long)n * cdiv(p->out_n / 2, Rows<N>::PPW);
-    const dim3 g2((unsigned)std::min<long long>(row_tiles, ROWS_WG));
+    const long long nwg = p->rows_wg > 0 ? std::min<long long>(row_tiles, p->rows_wg) : row_tiles;
     T_.begin(3);
-    hipLaunchKernelGGL((k_rows<N>), g2, dim3(Rows<N>::THREADS), Rows<N>::LDS, st, a);
+    hipLaunchKernelGGL((k_rows<N>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), Rows<N>::LDS, st, a);
     T_.end();
   }
   return launched();

@@ -237,6 +237,67 @@ __device__ __forceinline__ void stockham_stage(float2* buf, int lane, const floa
   wave_sync();
 }
 
+// Last stage of the transform with the outputs handed to emit(q, X[q]) from
+// registers instead of being written back to LDS (q = j + r NS, so lanes emit
+// consecutive indices together and global stores stay coalesced).
+template <int N, int R, int NS, int SIGN, class Emit>
+__device__ __forceinline__ void stockham_last_emit(float2* buf, int lane, const float2* __restrict__ tw,
+                                                   Emit&& emit) {
+  static_assert(NS * R == N, "last stage");
+  constexpr int NB = N / R;
+  constexpr int PER = (NB + WAVE - 1) / WAVE;
+  constexpr bool RD_LIN = NB % 16 == 0;
+  constexpr int RD_STEP = NB + NB / 16;
+  float2 v[PER][R];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int j = lane + p * WAVE;
+    if (NB % WAVE == 0 || j < NB) {
+      if constexpr (RD_LIN) {
+        const int b = pad(j);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[p][r] = buf[b + r * RD_STEP];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[p][r] = buf[pad(j + r * NB)];
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int j = lane + p * WAVE;
+    if (NB % WAVE == 0 || j < NB) {
+      if constexpr (NS > 1) {
+        const float2* t1 = tw + j;                      // k = j in the last stage, STEP = 1
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = t1[(r - 1) * j];
+          if (SIGN < 0) w.y = -w.y;
+          v[p][r] = cmul(v[p][r], w);
+        }
+      }
+      dft<R, SIGN>(v[p]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) emit(j + r * NS, v[p][r]);
+    }
+  }
+}
+
+// Whole transform with the last stage emitting (see stockham_last_emit). The
+// buffer is left holding the input of the last stage.
+template <int N, int SIGN, int NS = 1, class Emit>
+__device__ __forceinline__ void wave_fft_emit(float2* buf, int lane, const float2* __restrict__ tw,
+                                              Emit&& emit) {
+  constexpr int R = pick_radix(N / NS);
+  static_assert(R != 0, "length not supported by the radix set");
+  if constexpr (NS * R == N) {
+    stockham_last_emit<N, R, NS, SIGN>(buf, lane, tw, emit);
+  } else {
+    stockham_stage<N, R, NS, SIGN>(buf, lane, tw);
+    wave_fft_emit<N, SIGN, NS * R>(buf, lane, tw, emit);
+  }
+}
+
 template <int N, int SIGN, int NS = 1>
 __device__ __forceinline__ void wave_fft(float2* buf, int lane, const float2* __restrict__ tw) {
   if constexpr (NS < N) {

@@ -409,10 +409,10 @@ __device__ __forceinline__ const float2* stage_twiddles(float2* lds_tw) {
   }
 }
 
-template <int N>
+template <int N, int CPW_ = cols_per_wg(N)>
 struct Cols {
   static constexpr int STRIDE = padded_len(N);                // complex per column buffer
-  static constexpr int CPW = cols_per_wg(N);
+  static constexpr int CPW = CPW_;
   static constexpr int THREADS = CPW * WAVE;
   static constexpr int TW = TwLds<N>::ON ? N : 0;             // complex twiddles in LDS
   static size_t lds_bytes(bool counts) {
@@ -427,13 +427,12 @@ struct Cols {
 // The 1D grid is laid out so that all column tiles of an image share one XCD
 // (workgroup L runs on XCD L mod 8): the image's visibility row and the
 // timestep's sorted lists are then fetched into a single L2.
-template <int N, int MODE, bool UNI>
-__global__ void __launch_bounds__(Cols<N>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
-k_grid_cols(ImgArgs a) {
+template <int N, int MODE, bool UNI, int CPW = cols_per_wg(N)>
+__global__ void __launch_bounds__((Cols<N, CPW>::THREADS)) k_grid_cols(ImgArgs a) {
   extern __shared__ float4 lds_raw[];
-  __shared__ int red[2 * Cols<N>::CPW];
+  __shared__ int red[2 * CPW];
+  using C_ = Cols<N, CPW>;
   constexpr int H = N / 2;
-  constexpr int CPW = Cols<N>::CPW;
   constexpr bool CNT = UNI || MODE == MODE_GRID;
   const int L = blockIdx.x;
   const int r8 = L >> 3;
@@ -441,8 +440,8 @@ k_grid_cols(ImgArgs a) {
   const int tile = r8 % a.ntiles;
   if (li >= a.nimg) return;                          // padding of the last group of 8 images
   float2* lds = reinterpret_cast<float2*>(lds_raw);
-  float2* ltw = lds + CPW * Cols<N>::STRIDE;
-  int* lcnt = reinterpret_cast<int*>(ltw + Cols<N>::TW);
+  float2* ltw = lds + CPW * C_::STRIDE;
+  int* lcnt = reinterpret_cast<int*>(ltw + C_::TW);
   const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   const int img = a.img0 + li;
   const int t = img / a.C, ch = img - t * a.C;
@@ -458,12 +457,12 @@ k_grid_cols(ImgArgs a) {
   const int col = c0 + wave;                        // MODE_IMAGE: 0..H-1, MODE_GRID: 0..N-1
   const bool active = col < ncols;
   const int cs = MODE == MODE_IMAGE ? col : (col < H ? col : col - N);  // signed u cell
-  float2* buf = lds + wave * Cols<N>::STRIDE;
+  float2* buf = lds + wave * C_::STRIDE;
   int* cnt = CNT ? lcnt + wave * N : nullptr;
   const double s = cells_per_metre(a.freq[ch], a.ndx);
   const float2* tw = MODE == MODE_IMAGE ? stage_twiddles<N>(ltw) : nullptr;
 
-  for (int r = lane; r < Cols<N>::STRIDE; r += WAVE) buf[r] = make_float2(0.f, 0.f);
+  for (int r = lane; r < C_::STRIDE; r += WAVE) buf[r] = make_float2(0.f, 0.f);
   if (CNT)
     for (int r = lane; r < N; r += WAVE) cnt[r] = 0;
   wave_sync();
@@ -510,15 +509,14 @@ k_grid_cols(ImgArgs a) {
 
   if (MODE == MODE_IMAGE) {
     if (active) {
-      wave_fft<N, +1>(buf, lane, tw);
-      // rows of the cutout: output row m holds v-frequency q = (m - M/2) mod N
+      // rows of the cutout straight from the last stage: output row m holds
+      // v-frequency q = (m - M/2) mod N
       float2* dst = a.half + ((size_t)li * H + col) * a.M;
-      const int M = a.M;
-      for (int m = lane; m < M; m += WAVE) {
-        int q = m - M / 2;
-        q = q < 0 ? q + N : q;
-        dst[m] = buf[pad(q)];
-      }
+      const int hm = a.M / 2;
+      wave_fft_emit<N, +1>(buf, lane, tw, [&](int q, float2 v) {
+        if (q < hm) dst[q + hm] = v;
+        else if (q >= N - hm) dst[q - (N - hm)] = v;
+      });
     }
   } else {
     // write the CPW-column tile row by row (CPW consecutive cells per row)
@@ -527,7 +525,7 @@ k_grid_cols(ImgArgs a) {
     for (int e = threadIdx.x; e < N * CPW; e += blockDim.x) {
       const int r = e / CPW, w = e % CPW;
       if (c0 + w < N) {
-        g[(size_t)r * N + c0 + w] = lds[w * Cols<N>::STRIDE + pad(r)];
+        g[(size_t)r * N + c0 + w] = lds[w * C_::STRIDE + pad(r)];
         if (gc) gc[(size_t)r * N + c0 + w] = lcnt[w * N + r];
       }
     }
@@ -640,16 +638,18 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
     const int pair = p0 + wave;
     if (pair < npair) {
       float2* z = lds + wave * ST;
-      wave_fft<N, +1>(z, lane_i, tw);
       float* r0 = a.images + ((size_t)img * M + 2 * pair) * M;
       float* r1 = r0 + M;
-      for (int l = lane_i; l < M; l += WAVE) {
-        int q = l - M / 2;
-        q = q < 0 ? q + N : q;
-        const float2 v = z[pad(q)];
-        r0[l] = v.x * scale;
-        r1[l] = v.y * scale;
-      }
+      const int hm = M / 2;
+      // image columns of the cutout straight from the last stage: column l
+      // holds u-frequency q = (l - M/2) mod N; row 2p is Re z, row 2p+1 is Im z
+      wave_fft_emit<N, +1>(z, lane_i, tw, [&](int q, float2 v) {
+        const int l = q < hm ? q + hm : q - (N - hm);
+        if (q < hm || q >= N - hm) {
+          r0[l] = v.x * scale;
+          r1[l] = v.y * scale;
+        }
+      });
     }
   }
 }

@@ -76,7 +76,8 @@ def _image(lib, p, inp, images=FAKE, ws=None, nbytes=0):
     (dict(pixscale=0.0), E_ARG), (dict(pixscale=float("nan")), E_ARG),
     (dict(pixscale=float("inf")), E_ARG), (dict(pixscale=-1.0), E_ARG),
     (dict(weighting=2), E_ARG), (dict(norm=5), E_ARG), (dict(vis_type=3), E_ARG),
-    (dict(chunk_images=-2), E_ARG),
+    (dict(chunk_images=-2), E_ARG), (dict(cols_per_wg=3), E_ARG), (dict(cols_per_wg=16), E_ARG),
+    (dict(rows_wg=-1), E_ARG),
 ])
 def test_problem_validation(lib, kw, code):
     assert _image(lib, _prob(**kw), _inputs()) == code

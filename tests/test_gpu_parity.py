@@ -133,6 +133,18 @@ def test_bitwise_repeatable_and_chunk_invariant():
     assert torch.equal(a, b) and torch.equal(a, c) and torch.equal(a, e)
 
 
+@pytest.mark.parametrize("name", ["allsky180", "wide1024"])
+def test_tunables_give_identical_bits(name):
+    # tile width regroups integer partial sums only; the row grid only reorders tiles
+    w, _ = _grid_case(name)
+    d = inputs(w)
+    ref, _ = run_image(w, d, chunk_images=0, cols_per_wg=0, rows_wg=0)
+    for cpw in (2, 4, 8):
+        for rwg in (0, 7, 512):
+            got, _ = run_image(w, d, chunk_images=3, cols_per_wg=cpw, rows_wg=rwg)
+            assert torch.equal(got, ref), (cpw, rwg)
+
+
 def test_ragged_batch_equals_per_image_calls():
     w = synth.station_allsky(n_time=3, n_chan=2)
     d = inputs(w)
