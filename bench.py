@@ -162,6 +162,10 @@ def summarize(out_dir):
     f_fetch = copy_bytes / (cf * 1024.0)
     f_write = copy_bytes / (cw * 1024.0)
     imgs = 512
+    sys.path.insert(0, ROOT)
+    from paper_2405_13478_amd import synth
+    ncz = float(nonzero_columns(synth.widefield(n_time=10, n_chan=768), slice(0, 10)).mean())
+    alg = {"grid_cols": 8128 * 8 + ncz * 512 * 8, "rows": ncz * 512 * 8 + 512 * 512 * 4}
     res = {"workload": "widefield 1024^2 -> 512^2, 8128 baselines, 512 images per launch",
            "csrc_digest": digest, "copy_calibration": {"bytes": copy_bytes, "FETCH_SIZE_KiB": cf,
                                                       "WRITE_SIZE_KiB": cw, "fetch_scale": f_fetch,
@@ -174,16 +178,17 @@ def summarize(out_dir):
     md += ["", f"Copy calibration: FETCH_SIZE {cf:.1f} KiB and WRITE_SIZE {cw:.1f} KiB for 1 GiB moved "
            f"-> scale {f_fetch:.4f} (fetch), {f_write:.4f} (write).", "",
            f"Library sources digest: `{digest}`", "",
+           "Algorithmic bytes per image count the visibilities and the non-empty half-spectrum columns "
+           f"(mean {ncz:.1f} of 512 for this batch) that the kernels must move.", "",
            "| kernel | dispatches | FETCH KiB | WRITE KiB | HBM bytes / launch (scaled) | per image | algorithmic per image |",
            "|---|---|---|---|---|---|---|"]
-    alg = {"grid_cols": 8128 * 8 + 512 * 512 * 8, "rows": 512 * 512 * 8 + 512 * 512 * 4}
     for name, key in KERNEL_KEYS.items():
         fm, n = _counter_mean(fe, key, "FETCH_SIZE")
         wm, _ = _counter_mean(wr, key, "WRITE_SIZE")
         tb = (fm * f_fetch + wm * f_write) * 1024.0
         res["kernels"][name] = {"FETCH_SIZE_KiB": fm, "WRITE_SIZE_KiB": wm, "dispatches": n,
                                 "hbm_bytes_per_launch": tb, "images_per_launch": imgs}
-        md.append(f"| {name} (`{key}`) | {n} | {fm:.1f} | {wm:.1f} | {tb:.4g} | {tb / imgs:.4g} | {alg[name]} |")
+        md.append(f"| {name} (`{key}`) | {n} | {fm:.1f} | {wm:.1f} | {tb:.4g} | {tb / imgs:.4g} | {alg[name]:.4g} |")
     dom = "grid_cols"
     res["kernel"] = dom
     res["hbm_bytes_per_launch"] = res["kernels"][dom]["hbm_bytes_per_launch"]
@@ -275,9 +280,15 @@ def bench_images(args, np, torch, blink, synth, dev):
     images = torch.empty((n_img, M, M), dtype=torch.float32, device=dev)   # reused per step
     ws_cache = {}
 
+    tunings = {}
+
     def make_run(v, scale, vbytes):
+        # launch shapes: explicit flags win, else the autotuner's cache for this shape
+        tun = blink.blink.tuning_for(N, M, B, w.weighting, blink.blink._vis_type(v), args.chunk,
+                                     args.cols_per_wg, args.rows_wg)
+        tunings[vbytes] = tun
         p = blink.blink.make_problem(v[:TT], uvw[:TT], freq, N, w.pixscale, M, w.weighting, w.norm,
-                                     None, args.chunk)
+                                     None, **tun)
         ws_cache[vbytes] = ws = blink.workspace(p, blink.CALL_IMAGE, dev)
 
         def run(k, tm):
@@ -285,7 +296,7 @@ def bench_images(args, np, torch, blink, synth, dev):
             sl = slice(b * TT, (b + 1) * TT)
             blink.image_batch(v[sl], uvw[sl], freq, grid_n=N, pixscale=w.pixscale, out_n=M,
                               weighting=w.weighting, norm=w.norm, flags=None if flags is None else flags[sl],
-                              vis_scale=scale, chunk_images=args.chunk, images=images, ws=ws, times=tm)
+                              vis_scale=scale, images=images, ws=ws, times=tm, **tun)
         return run
 
     ncz = np.concatenate([nonzero_columns(w, slice(b * TT, (b + 1) * TT))
@@ -369,7 +380,7 @@ def bench_images(args, np, torch, blink, synth, dev):
         "data": "synthetic",
         "config": {"workload": DESCRIPTION[args.workload], "images_per_step": n_img,
                    "timesteps_per_step": TT, "grid_n": N, "out_n": M, "baselines": B,
-                   "channels": w.n_chan, "chunk_images": args.chunk},
+                   "channels": w.n_chan, "launch": tunings.get(8)},
         "visibilities_per_s": round(img_per_s * unflagged, 1),
         "nonzero_half_spectrum_columns_mean": round(ncz_mean, 2),
         "path_hbm_frac_algorithmic": res["path_hbm_frac_algorithmic"],
@@ -464,7 +475,9 @@ def main():
     ap.add_argument("--timesteps-per-step", type=int, default=None)
     ap.add_argument("--timesteps", type=int, default=None,
                     help="timesteps of the job generated into HBM (default: the whole widefield job)")
-    ap.add_argument("--chunk", type=int, default=0, help="images per internal chunk (0 = library default)")
+    ap.add_argument("--chunk", type=int, default=None, help="images per internal chunk (default: tuned)")
+    ap.add_argument("--cols-per-wg", type=int, default=None, help="column kernel tile width (default: tuned)")
+    ap.add_argument("--rows-wg", type=int, default=None, help="persistent row-pass grid (default: tuned)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=None)
     ap.add_argument("--plain-loop", type=int, default=256,
