@@ -34,7 +34,9 @@
  * - Cells per metre of channel c: s_c = (freq_hz[c] * (N * pixscale)) / c0 with
  *   c0 = 299792458 m/s, evaluated in IEEE double in that order (Eq. 9 gives
  *   the cell du = 1/(N dx) wavelengths; Sec. 5.2.4 computes the channel
- *   frequency and wavelength in double).
+ *   frequency and wavelength in double). freq_hz must be finite and > 0
+ *   (device memory, so not checked): other values give unspecified images,
+ *   but every memory access stays within the arrays.
  * - Cell of baseline b: i_u = rint(u * s_c), i_v = rint(v * s_c) (one double
  *   product, round half to even). The baseline is kept iff it is not flagged,
  *   u and v are finite, |i_u| < N/2 and |i_v| < N/2; kept baselines are

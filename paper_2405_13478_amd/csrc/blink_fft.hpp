@@ -173,6 +173,20 @@ __host__ __device__ constexpr bool plan_ok(int n) {
   return true;
 }
 
+// Twiddles of the stages: one table per stage after the first, laid out
+// [(r - 1) * NS + k] = w_{NS R}^(k r), concatenated in stage order, so that for
+// a fixed r the lanes of a wavefront read consecutive entries.
+__host__ __device__ constexpr int tw_entries_before(int n, int ns) {
+  int total = 0, cur = 1;
+  while (cur < ns) {
+    const int r = pick_radix(n / cur);
+    if (cur > 1) total += (r - 1) * cur;
+    cur *= r;
+  }
+  return total;
+}
+__host__ __device__ constexpr int tw_entries(int n) { return tw_entries_before(n, n); }
+
 // One Stockham stage of radix R after NS points have been combined:
 // butterfly j reads x[j + r N/R], twiddles by w_{NS R}^(SIGN (j mod NS) r),
 // applies the length-R DFT and writes y[(j / NS) NS R + (j mod NS) + r NS].
@@ -213,11 +227,11 @@ __device__ __forceinline__ void stockham_stage(float2* buf, int lane, const floa
     if (NB % WAVE == 0 || j < NB) {
       const int k = j % NS;
       if constexpr (NS > 1) {
-        constexpr int STEP = N / (NS * R);
-        const float2* t1 = tw + k * STEP;
+        constexpr int TW0 = tw_entries_before(N, NS);             // folded at compile time
+        const float2* t1 = tw + TW0 + k;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 w = t1[(r - 1) * k * STEP];
+          float2 w = t1[(r - 1) * NS];
           if (SIGN < 0) w.y = -w.y;
           v[p][r] = cmul(v[p][r], w);
         }
@@ -268,10 +282,11 @@ __device__ __forceinline__ void stockham_last_emit(float2* buf, int lane, const 
     const int j = lane + p * WAVE;
     if (NB % WAVE == 0 || j < NB) {
       if constexpr (NS > 1) {
-        const float2* t1 = tw + j;                      // k = j in the last stage, STEP = 1
+        constexpr int TW0 = tw_entries_before(N, NS);
+        const float2* t1 = tw + TW0 + j;                          // k = j in the last stage
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 w = t1[(r - 1) * j];
+          float2 w = t1[(r - 1) * NS];
           if (SIGN < 0) w.y = -w.y;
           v[p][r] = cmul(v[p][r], w);
         }

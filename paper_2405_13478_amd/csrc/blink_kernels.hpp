@@ -268,6 +268,11 @@ struct ImgArgs {
 
 // bnd[c + N/2] = first sorted position j with clamp(rint(u_j s)) >= c for
 // c in [-N/2, N/2 + 1]; entry N + 1 is always n_valid. One workgroup per image.
+// The clamped cell is non-decreasing along the sorted order (s > 0), so each
+// bound is found either by one pass over the list, marking where the cell
+// steps up, or - when the list is much longer than the N + 2 bounds - by a
+// binary search per bound. Both give that first position. For s <= 0 or a
+// non-finite s every bound still lies in [0, n_valid].
 __global__ void __launch_bounds__(256) k_bounds(ImgArgs a) {
   const int img = blockIdx.x;
   const int t = img / a.C, ch = img - t * a.C;
@@ -280,13 +285,24 @@ __global__ void __launch_bounds__(256) k_bounds(ImgArgs a) {
     const double x = rint(su[j] * s);
     return (int)fmin(fmax(x, (double)-H), (double)H);
   };
-  for (int j = threadIdx.x; j < nv; j += blockDim.x) {
-    const int cj = col(j);
-    const int cp = j == 0 ? -H - 1 : col(j - 1);
-    for (int c = cp + 1; c <= cj; ++c) bnd[c + H] = j;
-  }
   const int clast = nv == 0 ? -H - 1 : col(nv - 1);
-  for (int c = clast + 1 + (int)threadIdx.x; c <= H + 1; c += blockDim.x) bnd[c + H] = nv;
+  if (nv > 16 * (a.N + 2)) {
+    for (int c = (int)threadIdx.x - H; c <= H + 1; c += blockDim.x) {
+      int lo = 0, hi = nv;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (col(mid) >= c) hi = mid; else lo = mid + 1;
+      }
+      bnd[c + H] = lo;
+    }
+  } else {
+    for (int j = threadIdx.x; j < nv; j += blockDim.x) {
+      const int cj = col(j);
+      const int cp = j == 0 ? -H - 1 : col(j - 1);
+      for (int c = cp + 1; c <= cj; ++c) bnd[c + H] = j;
+    }
+    for (int c = clast + 1 + (int)threadIdx.x; c <= H + 1; c += blockDim.x) bnd[c + H] = nv;
+  }
   // every entry lies in a column |c| <= max(|first|, |last|) of the sorted order
   if (threadIdx.x == 0) a.ncz[img] = nv == 0 ? 0 : min(H, max(clast, -col(0)) + 1);
 }
@@ -401,11 +417,12 @@ struct TwLds { static constexpr bool ON = N <= 1024; };
 template <int N>
 __device__ __forceinline__ const float2* stage_twiddles(float2* lds_tw) {
   if constexpr (TwLds<N>::ON) {
-    const float2* g = TwTable<N>::get();
-    for (int i = threadIdx.x; i < N; i += blockDim.x) lds_tw[i] = g[i];
+    const float2* g = TwTable<N>::stages();
+    constexpr int NTW = tw_entries(N);
+    for (int i = threadIdx.x; i < NTW; i += blockDim.x) lds_tw[i] = g[i];
     return lds_tw;      // visible after the caller's next __syncthreads
   } else {
-    return TwTable<N>::get();
+    return TwTable<N>::stages();
   }
 }
 
@@ -414,7 +431,7 @@ struct Cols {
   static constexpr int STRIDE = padded_len(N);                // complex per column buffer
   static constexpr int CPW = CPW_;
   static constexpr int THREADS = CPW * WAVE;
-  static constexpr int TW = TwLds<N>::ON ? N : 0;             // complex twiddles in LDS
+  static constexpr int TW = TwLds<N>::ON ? tw_entries(N) : 0; // complex twiddles in LDS
   static size_t lds_bytes(bool counts) {
     return (size_t)(CPW * STRIDE + TW) * sizeof(float2) + (counts ? (size_t)CPW * N * sizeof(int) : 0);
   }
@@ -548,10 +565,12 @@ __global__ void k_grid_finish(ImgArgs a, int n_img) {
 // ============================================================== row pass
 template <int N>
 struct Rows {
-  static constexpr int STRIDE = padded_len(N) + 4;   // +4 complex shifts buffers across banks
+  // buffer stride of 4 mod 32 complex: the workgroup's PPW buffers start on
+  // different bank groups, so filling them side by side is conflict-free
+  static constexpr int STRIDE = padded_len(N) + ((4 - padded_len(N) % 32) + 32) % 32;
   static constexpr int PPW = N <= 1024 ? 8 : (N <= 2048 ? 4 : 2);  // row pairs (waves) per WG
   static constexpr int THREADS = PPW * WAVE;
-  static constexpr int TW = TwLds<N>::ON ? N : 0;
+  static constexpr int TW = TwLds<N>::ON ? tw_entries(N) : 0;
   static constexpr size_t LDS = (size_t)(PPW * STRIDE + TW) * sizeof(float2);
 };
 
@@ -674,7 +693,7 @@ __global__ void __launch_bounds__(Fft2<N>::THREADS) k_fft_rows(const float2* in,
   const float2* s = in + row * N;
   for (int i = lane; i < N; i += WAVE) z[pad(i)] = s[i];
   wave_sync();
-  wave_fft<N, SIGN>(z, lane, TwTable<N>::get());
+  wave_fft<N, SIGN>(z, lane, TwTable<N>::stages());
   float2* d = out + row * N;
   for (int i = lane; i < N; i += WAVE) d[i] = z[pad(i)];
 }
@@ -692,7 +711,7 @@ __global__ void __launch_bounds__(Fft2<N>::THREADS) k_fft_cols(float2* data) {
     if (c0 + w < N) lds[w * Fft2<N>::STRIDE + pad(r)] = img[(size_t)r * N + c0 + w];
   }
   __syncthreads();
-  if (c0 + wave < N) wave_fft<N, SIGN>(lds + wave * Fft2<N>::STRIDE, lane, TwTable<N>::get());
+  if (c0 + wave < N) wave_fft<N, SIGN>(lds + wave * Fft2<N>::STRIDE, lane, TwTable<N>::stages());
   __syncthreads();
   for (int e = threadIdx.x; e < N * VPW; e += blockDim.x) {
     const int r = e / VPW, w = e % VPW;
