@@ -296,7 +296,14 @@ blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t s
     const long long row_tiles = (long long)n * cdiv(p->out_n / 2, Rows<N>::PPW);
     const long long nwg = p->rows_wg > 0 ? std::min<long long>(row_tiles, p->rows_wg) : row_tiles;
     T_.begin(3);
-    hipLaunchKernelGGL((k_rows<N>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), Rows<N>::LDS, st, a);
+    if constexpr (blocks_aligned(N)) {
+      if ((p->out_n / 2) % WAVE == 0)
+        hipLaunchKernelGGL((k_rows<N, true>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), Rows<N>::LDS, st, a);
+      else
+        hipLaunchKernelGGL((k_rows<N, false>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), Rows<N>::LDS, st, a);
+    } else {
+      hipLaunchKernelGGL((k_rows<N, false>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), Rows<N>::LDS, st, a);
+    }
     T_.end();
   }
   return launched();

@@ -8,9 +8,24 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace blink {
 
 constexpr int WAVE = 64;
+
+template <int V>
+using ic = std::integral_constant<int, V>;
+
+// f(ic<B>{}), f(ic<B + 1>{}), ..., f(ic<E - 1>{}): a loop whose index is a
+// compile-time constant in the body.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(ic<B>{});
+    static_for<B + 1, E>(f);
+  }
+}
 
 // ---------------------------------------------------------------- complex
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -251,9 +266,12 @@ __device__ __forceinline__ void stockham_stage(float2* buf, int lane, const floa
   wave_sync();
 }
 
-// Last stage of the transform with the outputs handed to emit(q, X[q]) from
-// registers instead of being written back to LDS (q = j + r NS, so lanes emit
-// consecutive indices together and global stores stay coalesced).
+// Last stage of the transform with the outputs handed to emit(ic<QB>, X)
+// from registers instead of being written back to LDS. Each call covers the
+// wavefront's block of consecutive frequencies q = QB + lane, QB a
+// compile-time constant (lanes beyond the stage's butterflies are inactive),
+// so global stores stay coalesced and the caller can decide per block with
+// wave-uniform tests.
 template <int N, int R, int NS, int SIGN, class Emit>
 __device__ __forceinline__ void stockham_last_emit(float2* buf, int lane, const float2* __restrict__ tw,
                                                    Emit&& emit) {
@@ -277,8 +295,8 @@ __device__ __forceinline__ void stockham_last_emit(float2* buf, int lane, const 
       }
     }
   }
-#pragma unroll
-  for (int p = 0; p < PER; ++p) {
+  static_for<0, PER>([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
     const int j = lane + p * WAVE;
     if (NB % WAVE == 0 || j < NB) {
       if constexpr (NS > 1) {
@@ -292,10 +310,70 @@ __device__ __forceinline__ void stockham_last_emit(float2* buf, int lane, const 
         }
       }
       dft<R, SIGN>(v[p]);
-#pragma unroll
-      for (int r = 0; r < R; ++r) emit(j + r * NS, v[p][r]);
+      static_for<0, R>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        emit(ic<p * WAVE + r * NS>{}, v[p][r]);
+      });
     }
+  });
+}
+
+// base[i] = v with the byte offset formed in 32 bits, so that the store can
+// take a scalar base address and a 32-bit per-lane offset (i * sizeof(T) must
+// stay below 4 GiB).
+template <class T>
+__device__ __forceinline__ void store_at(T* base, unsigned i, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T)) = v;
+}
+
+// Centred cutout of a length-N spectrum: frequency q goes to position q + hm
+// if q < hm, to q - (N - hm) if q >= N - hm, and is dropped otherwise (2 hm
+// kept points; output position hm holds frequency 0). For the block
+// q = QB + lane the tests are wave-uniform unless the block straddles a
+// boundary; st(pos) performs the store. Positions are unsigned so that the
+// store can address a scalar base plus a 32-bit lane offset.
+template <int N, int QB, class Store>
+__device__ __forceinline__ void cutout_block(unsigned lane, int hm, Store&& st) {
+  if (QB + WAVE <= hm) {
+    st((unsigned)(QB + hm) + lane);
+  } else if (QB >= N - hm) {
+    st((unsigned)(QB - (N - hm)) + lane);
+  } else if (QB < hm || QB + WAVE > N - hm) {
+    const int q = QB + (int)lane;
+    if (q < hm) st((unsigned)(q + hm));
+    else if (q >= N - hm) st((unsigned)(q - (N - hm)));
+    // keeps the compiler from merging these per-lane stores with the block
+    // stores above, which would turn their scalar offsets into per-lane ones
+    asm volatile("" ::: "memory");
   }
+}
+
+// Per-lane form of the same cutout (no block tests): fewest registers.
+template <int N, int QB, class Store>
+__device__ __forceinline__ void cutout_lane(unsigned lane, int hm, Store&& st) {
+  const int q = QB + (int)lane;
+  if (q < hm || q >= N - hm) st((unsigned)(q < hm ? q + hm : q - (N - hm)));
+}
+
+// Stride of the last stage of the length-n plan (the NS it is entered with).
+__host__ __device__ constexpr int last_stage_ns(int n) {
+  int cur = 1;
+  while (n / cur / pick_radix(n / cur) > 1) cur *= pick_radix(n / cur);
+  return cur;
+}
+// True when every emitted block q = QB + lane of the last stage starts at a
+// multiple of the wavefront width and has all lanes active.
+__host__ __device__ constexpr bool blocks_aligned(int n) {
+  return plan_ok(n) && last_stage_ns(n) % WAVE == 0 && (n / pick_radix(n / last_stage_ns(n))) % WAVE == 0;
+}
+
+// Cutout store for blocks aligned to the wavefront width with hm a multiple
+// of it as well: each block is wholly kept or wholly dropped.
+template <int N, int QB, class Store>
+__device__ __forceinline__ void cutout_block_aligned(unsigned lane, int hm, Store&& st) {
+  static_assert(QB % WAVE == 0, "block not aligned");
+  if (QB < hm) st((unsigned)(QB + hm) + lane);
+  else if (QB >= N - hm) st((unsigned)(QB - (N - hm)) + lane);
 }
 
 // Whole transform with the last stage emitting (see stockham_last_emit). The

@@ -459,7 +459,7 @@ __global__ void __launch_bounds__((Cols<N, CPW>::THREADS)) k_grid_cols(ImgArgs a
   float2* lds = reinterpret_cast<float2*>(lds_raw);
   float2* ltw = lds + CPW * C_::STRIDE;
   int* lcnt = reinterpret_cast<int*>(ltw + C_::TW);
-  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), lane = threadIdx.x % WAVE;
   const int img = a.img0 + li;
   const int t = img / a.C, ch = img - t * a.C;
   const int c0 = tile * CPW;
@@ -530,9 +530,8 @@ __global__ void __launch_bounds__((Cols<N, CPW>::THREADS)) k_grid_cols(ImgArgs a
       // v-frequency q = (m - M/2) mod N
       float2* dst = a.half + ((size_t)li * H + col) * a.M;
       const int hm = a.M / 2;
-      wave_fft_emit<N, +1>(buf, lane, tw, [&](int q, float2 v) {
-        if (q < hm) dst[q + hm] = v;
-        else if (q >= N - hm) dst[q - (N - hm)] = v;
+      wave_fft_emit<N, +1>(buf, lane, tw, [&](auto qb, float2 v) {
+        cutout_block<N, decltype(qb)::value>(lane, hm, [&](unsigned m) { store_at(dst, m, v); });
       });
     }
   } else {
@@ -585,8 +584,12 @@ struct Rows {
 // half-spectrum slice of the next tile is already in flight into registers,
 // so the HBM latency of the loads hides behind the arithmetic of the previous
 // tile (larger N would need too many registers and loads per tile instead).
-template <int N>
+// AL: the cutout half-width M/2 is a multiple of the wavefront width and the
+// plan's last-stage blocks are aligned (blocks_aligned), so each block of 64
+// output columns is stored or skipped whole.
+template <int N, bool AL>
 __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
+  static_assert(!AL || blocks_aligned(N), "aligned cutout needs aligned blocks");
   extern __shared__ float4 lds_raw[];
   constexpr int H = N / 2;
   constexpr int PPW = Rows<N>::PPW;
@@ -596,7 +599,7 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
   constexpr bool PREF = EPT <= 8;
   constexpr int NPRE = PREF ? EPT : 1;
   float2* lds = reinterpret_cast<float2*>(lds_raw);
-  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), lane = threadIdx.x % WAVE;
   const int M = a.M;
   const int npair = M / 2;
   const int ntr = (npair + PPW - 1) / PPW;           // row tiles per image
@@ -659,15 +662,17 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
       float2* z = lds + wave * ST;
       float* r0 = a.images + ((size_t)img * M + 2 * pair) * M;
       float* r1 = r0 + M;
-      const int hm = M / 2;
+      int hm = M / 2;
+      asm volatile("" : "+s"(hm));   // block tests stay inside the loop (hoisted they spill)
       // image columns of the cutout straight from the last stage: column l
       // holds u-frequency q = (l - M/2) mod N; row 2p is Re z, row 2p+1 is Im z
-      wave_fft_emit<N, +1>(z, lane_i, tw, [&](int q, float2 v) {
-        const int l = q < hm ? q + hm : q - (N - hm);
-        if (q < hm || q >= N - hm) {
-          r0[l] = v.x * scale;
-          r1[l] = v.y * scale;
-        }
+      wave_fft_emit<N, +1>(z, lane_i, tw, [&](auto qb, float2 v) {
+        auto st = [&](unsigned l) {
+          store_at(r0, l, v.x * scale);
+          store_at(r1, l, v.y * scale);
+        };
+        if constexpr (AL) cutout_block_aligned<N, decltype(qb)::value>(lane_i, hm, st);
+        else cutout_lane<N, decltype(qb)::value>(lane_i, hm, st);
       });
     }
   }

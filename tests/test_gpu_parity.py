@@ -112,6 +112,24 @@ def test_image_norm_and_cutout(norm, out_n):
     assert rel_l2(img.cpu().numpy()[0], ref[0]) <= REL_L2_FP32
 
 
+@pytest.mark.parametrize("out_n", [512, 256, 200, 130, 2])
+def test_cutout_alignment_512(out_n):
+    """Cutouts whose half-width is a multiple of 64 take the block-store path
+    of the row pass, others the per-lane one; blocks that straddle the cutout
+    edge take the per-lane path of the column pass. All match the oracle."""
+    print(f"\n[gpu] 512^2 grid, cutout {out_n}", flush=True)
+    w = synth.widefield(n_time=1, n_chan=2, chan_stride=300)
+    w.grid_n = 512
+    w.out_n = out_n
+    w.pixscale = synth.oversampled_pixscale(3000.0, float(w.freq_hz.max()))
+    d = inputs(w)
+    img, wsum = run_image(w, d)
+    ref, W = oracle_images(w, d["vis"].cpu().numpy(), range(w.n_img))
+    errs = per_image_rel_l2(img.cpu().numpy(), ref)
+    assert max(errs) <= REL_L2_FP32, errs
+    assert np.array_equal(wsum.cpu().numpy(), W.astype(np.float32))
+
+
 def test_point_source_at_phase_centre_gives_centred_peak():
     w = synth.plain_single()
     d = inputs(w)
