@@ -212,30 +212,15 @@ __host__ __device__ constexpr int tw_entries(int n) { return tw_entries_before(n
 // base + r * stride is pad(base) + r * (stride + stride / 16), and for NS = 1
 // with R dividing 16 it is pad(j R) + r, so every access is a per-lane base
 // plus a compile-time offset that folds into the LDS instruction.
+// Second half of a stage: twiddle, DFT and write of the butterflies whose
+// inputs v[p][r] = x[j + r N/R] (j = lane + 64 p) are already in registers.
 template <int N, int R, int NS, int SIGN>
-__device__ __forceinline__ void stockham_stage(float2* buf, int lane, const float2* __restrict__ tw) {
+__device__ __forceinline__ void stockham_stage_regs(float2* buf, int lane, const float2* __restrict__ tw,
+                                                    float2 (&v)[(N / R + WAVE - 1) / WAVE][R]) {
   constexpr int NB = N / R;
   constexpr int PER = (NB + WAVE - 1) / WAVE;
-  constexpr bool RD_LIN = NB % 16 == 0;                       // read offsets fold
   constexpr bool WR_LIN = NS % 16 == 0 || (NS == 1 && 16 % R == 0);   // write offsets fold
-  constexpr int RD_STEP = NB + NB / 16;
   constexpr int WR_STEP = NS == 1 ? 1 : NS + NS / 16;
-  float2 v[PER][R];
-#pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int j = lane + p * WAVE;
-    if (NB % WAVE == 0 || j < NB) {
-      if constexpr (RD_LIN) {
-        const int b = pad(j);
-#pragma unroll
-        for (int r = 0; r < R; ++r) v[p][r] = buf[b + r * RD_STEP];
-      } else {
-#pragma unroll
-        for (int r = 0; r < R; ++r) v[p][r] = buf[pad(j + r * NB)];
-      }
-    }
-  }
-  wave_sync();
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
     const int j = lane + p * WAVE;
@@ -264,6 +249,31 @@ __device__ __forceinline__ void stockham_stage(float2* buf, int lane, const floa
     }
   }
   wave_sync();
+}
+
+template <int N, int R, int NS, int SIGN>
+__device__ __forceinline__ void stockham_stage(float2* buf, int lane, const float2* __restrict__ tw) {
+  constexpr int NB = N / R;
+  constexpr int PER = (NB + WAVE - 1) / WAVE;
+  constexpr bool RD_LIN = NB % 16 == 0;                       // read offsets fold
+  constexpr int RD_STEP = NB + NB / 16;
+  float2 v[PER][R];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int j = lane + p * WAVE;
+    if (NB % WAVE == 0 || j < NB) {
+      if constexpr (RD_LIN) {
+        const int b = pad(j);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[p][r] = buf[b + r * RD_STEP];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[p][r] = buf[pad(j + r * NB)];
+      }
+    }
+  }
+  wave_sync();
+  stockham_stage_regs<N, R, NS, SIGN>(buf, lane, tw, v);
 }
 
 // Last stage of the transform with the outputs handed to emit(ic<QB>, X)

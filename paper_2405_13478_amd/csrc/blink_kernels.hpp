@@ -354,56 +354,84 @@ __device__ __forceinline__ float2 load_vis(const ImgArgs& a, size_t off, int b, 
 // gathers, then the LDS adds, so a wavefront keeps GU times more loads in
 // flight. Only this wavefront touches the column, so the LDS adds happen in a
 // fixed order (steps in sequence; within a step, sub-steps in sequence and
-// lanes in LDS order). Returns the kept direct and conjugate entries.
+// lanes in LDS order).
 constexpr int GU = 4;
 
-template <int N, bool COUNT>
-__device__ __forceinline__ int2 grid_points(const ImgArgs& a, float2* buf, int* cnt, int dlo, int dhi,
-                                            int clo, int chi, int t, int ch, double s, int lane) {
+struct ColSpan {                 // the sorted entries of one u-cell column
+  int dlo, dhi, clo, chi;        // direct range and mirror (conjugate) range
+  __device__ int nd() const { return dhi - dlo; }
+  __device__ int total() const { return (dhi - dlo) + (chi - clo); }
+};
+
+struct EntryStep {               // GU x 64 entries in registers
+  double sv[GU];
+  int bl[GU];
+  int row[GU];
+  float2 val[GU];
+  bool ok[GU], cj[GU];
+};
+
+// phase 1: sorted-list loads (v in metres and baseline index) of the step at i0
+__device__ __forceinline__ void step_keys(const ImgArgs& a, const ColSpan& c, int i0, int t, int lane,
+                                          EntryStep& e) {
   const size_t tb = (size_t)t * a.B;
-  const size_t vb = ((size_t)t * a.C + ch) * a.B;
-  const int nd = dhi - dlo;
-  const int total = nd + (chi - clo);
-  int kd = 0, kc = 0;
-  for (int i0 = 0; i0 < total; i0 += GU * WAVE) {
-    double sv[GU];
-    int bl[GU];
-    bool ok[GU], cj[GU];
+  const int nd = c.nd(), total = c.total();
 #pragma unroll
-    for (int u = 0; u < GU; ++u) {
-      const int i = i0 + u * WAVE + lane;
-      ok[u] = i < total;
-      cj[u] = i >= nd;
-      const int j = cj[u] ? clo + (i - nd) : dlo + i;
-      sv[u] = ok[u] ? a.sv[tb + j] : 0.0;
-      bl[u] = ok[u] ? a.perm[tb + j] : 0;
-    }
-    int row[GU];
-    float2 val[GU];
-#pragma unroll
-    for (int u = 0; u < GU; ++u) {
-      const double iv = rint(sv[u] * s);
-      ok[u] = ok[u] && fabs(iv) < (double)(N / 2);
-      int r = (int)iv;
-      if (cj[u]) r = -r;
-      row[u] = r < 0 ? r + N : r;
-      val[u] = ok[u] ? load_vis(a, vb + bl[u], bl[u], ch) : make_float2(0.f, 0.f);
-    }
-#pragma unroll
-    for (int u = 0; u < GU; ++u) {
-      if (ok[u]) {
-        float2 v = val[u];
-        if (cj[u]) v.y = -v.y;
-        float2* p = &buf[pad(row[u])];
-        atomicAdd(&p->x, v.x);
-        atomicAdd(&p->y, v.y);
-        if (COUNT) atomicAdd(&cnt[row[u]], 1);
-      }
-      kd += __popcll(__ballot(ok[u] && !cj[u]));
-      kc += __popcll(__ballot(ok[u] && cj[u]));
-    }
+  for (int u = 0; u < GU; ++u) {
+    const int i = i0 + u * WAVE + lane;
+    e.ok[u] = i < total;
+    e.cj[u] = i >= nd;
+    const int j = e.cj[u] ? c.clo + (i - nd) : c.dlo + i;
+    e.sv[u] = e.ok[u] ? a.sv[tb + j] : 0.0;
+    e.bl[u] = e.ok[u] ? a.perm[tb + j] : 0;
   }
-  return make_int2(kd, kc);
+}
+
+// phase 2: cell rows (FP64) and the visibility gathers of the kept entries
+template <int N>
+__device__ __forceinline__ void step_gather(const ImgArgs& a, int t, int ch, double s, EntryStep& e) {
+  const size_t vb = ((size_t)t * a.C + ch) * a.B;
+#pragma unroll
+  for (int u = 0; u < GU; ++u) {
+    const double iv = rint(e.sv[u] * s);
+    e.ok[u] = e.ok[u] && fabs(iv) < (double)(N / 2);
+    int r = (int)iv;
+    if (e.cj[u]) r = -r;
+    e.row[u] = r < 0 ? r + N : r;
+    e.val[u] = e.ok[u] ? load_vis(a, vb + e.bl[u], e.bl[u], ch) : make_float2(0.f, 0.f);
+  }
+}
+
+// phase 3: the LDS adds; kd / kc count the kept direct / conjugate entries
+template <bool COUNT>
+__device__ __forceinline__ void step_add(const EntryStep& e, float2* buf, int* cnt, int& kd, int& kc) {
+#pragma unroll
+  for (int u = 0; u < GU; ++u) {
+    if (e.ok[u]) {
+      float2 v = e.val[u];
+      if (e.cj[u]) v.y = -v.y;
+      float2* p = &buf[pad(e.row[u])];
+      atomicAdd(&p->x, v.x);
+      atomicAdd(&p->y, v.y);
+      if (COUNT) atomicAdd(&cnt[e.row[u]], 1);
+    }
+    kd += __popcll(__ballot(e.ok[u] && !e.cj[u]));
+    kc += __popcll(__ballot(e.ok[u] && e.cj[u]));
+  }
+}
+
+// All steps of a column from step i0 on; returns the kept direct and
+// conjugate entries (added to kd / kc).
+template <int N, bool COUNT>
+__device__ __forceinline__ void grid_steps(const ImgArgs& a, const ColSpan& c, int i0, float2* buf, int* cnt,
+                                           int t, int ch, double s, int lane, int& kd, int& kc) {
+  const int total = c.total();
+  for (; i0 < total; i0 += GU * WAVE) {
+    EntryStep e;
+    step_keys(a, c, i0, t, lane, e);
+    step_gather<N>(a, t, ch, s, e);
+    step_add<COUNT>(e, buf, cnt, kd, kc);
+  }
 }
 
 // u-cell columns (one wavefront each) per workgroup of the column kernels
@@ -487,10 +515,9 @@ __global__ void __launch_bounds__((Cols<N, CPW>::THREADS)) k_grid_cols(ImgArgs a
   int kept_b = 0, wcontrib = 0;
   if (active && cs != H && cs != -H) {
     const int* bnd = a.bnd + (size_t)img * (N + 2);
-    const int dlo = bnd[cs + H], dhi = bnd[cs + 1 + H];
-    const int clo = bnd[-cs + H], chi = bnd[-cs + 1 + H];
-    const int2 k2 = grid_points<N, CNT>(a, buf, cnt, dlo, dhi, clo, chi, t, ch, s, lane);
-    const int kd = k2.x, kc = k2.y;
+    const ColSpan span{bnd[cs + H], bnd[cs + 1 + H], bnd[-cs + H], bnd[-cs + 1 + H]};
+    int kd = 0, kc = 0;
+    grid_steps<N, CNT>(a, span, 0, buf, cnt, t, ch, s, lane, kd, kc);
     wave_sync();
     // baselines counted once: the direct entry of every cell column, plus the
     // conjugate entries of columns whose mirror the image path never visits
