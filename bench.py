@@ -110,7 +110,7 @@ PROFILE_CMDS = {
     "copy_write": "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'blink|copyBuffer' --output-format csv "
                   "-d OUT/pmc_copy_WRITE_SIZE -o copy -- python3 bench.py --copy-calibration",
 }
-KERNEL_KEYS = {"grid_cols": "k_grid_cols<1024, 0", "rows": "k_rows<1024>"}
+KERNEL_KEYS = {"grid_cols": "k_grid_cols<1024, 0", "rows": "k_rows<1024"}
 
 
 def _csv(path):
