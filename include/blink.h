@@ -51,6 +51,21 @@
  *   FFT shift (Sec. 5.2.2), times 1/W when norm = BLINK_NORM_WEIGHTS (W = 0
  *   gives zeros), then the central M x M cutout. Layout [m][l]: row follows
  *   v (m), column follows u (l), phase centre at [M/2][M/2].
+ * - Gridding kernel (kernel_support = W >= 1; the anti-aliasing convolution
+ *   that Sec. 4.4.1 describes and the paper's imager leaves out): a baseline
+ *   at the exact cell position x = (u s_c, v s_c) adds
+ *   C(i - x_u) C(j - x_v) V' to every cell with |i - x_u| <= W/2 and
+ *   |j - x_v| <= W/2 (and the same weight times conj(V') at the mirror
+ *   cells), C(d) = I0(beta sqrt(1 - (2d/W)^2)) / I0(beta). It is kept iff
+ *   that whole footprint satisfies |i| < N/2, |j| < N/2. Natural weighting
+ *   only: W = the sum of all weights added. Each image pixel at offset
+ *   (q_m, q_l) from the centre is divided by c(q_l/N) c(q_m/N), c the
+ *   kernel's continuous Fourier transform normalised to c(0) = 1:
+ *   c(xi) = [sinh(z)/z] / [sinh(beta)/beta], z = sqrt(beta^2 - (pi W xi)^2)
+ *   (sin(|z|)/|z| where pi W |xi| > beta). Weights are evaluated in FP32 from
+ *   the FP64 distances; blink_grid returns counts of contributions per cell.
+ *   Uniform weighting and blink_degrid_adjoint with a kernel return
+ *   BLINK_E_UNSUPPORTED.
  */
 #ifndef BLINK_H
 #define BLINK_H
@@ -101,6 +116,11 @@ typedef struct {
                          /* kernel: 0 = library default, else 2, 4 or 8                */
   int32_t rows_wg;       /* row pass: 0 = one workgroup per row tile, > 0 = that many  */
                          /* persistent workgroups walking the row tiles                */
+  int32_t kernel_support;/* gridding kernel: 0 = nearest cell (the paper's imager);   */
+                         /* 1..16 = separable Kaiser-Bessel of that support W in cells */
+                         /* with the image-domain correction (see below)               */
+  double  kernel_beta;   /* Kaiser-Bessel shape; < 0 = pi sqrt(0.5625 W^2 - 0.8)       */
+                         /* (needs W >= 2); ignored when kernel_support = 0            */
 } blink_problem;
 
 typedef struct {          /* device pointers; the optional ones may be NULL            */

@@ -34,6 +34,27 @@ bool n_supported(int n) {
 
 inline size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
+constexpr int KB_MAX_SUPPORT = 16;
+
+// pi sqrt(0.5625 W^2 - 0.8): the Kaiser-Bessel shape for a grid twice the
+// kept image (Beatty, Nishimura and Pauly 2005); negative when W is too small.
+double kb_default_beta(int w) {
+  const double q = 0.5625 * w * w - 0.8;
+  return q > 0 ? M_PI * sqrt(q) : -1.0;
+}
+
+// I0(x) by its power series sum_k ((x/2)^2)^k / (k!)^2 (all terms positive;
+// run to double rounding), for the kernel's normalisation 1 / I0(beta).
+double bessel_i0(double x) {
+  const double q = 0.25 * x * x;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 500 && term > 1e-17 * sum; ++k) {
+    term *= q / ((double)k * k);
+    sum += term;
+  }
+  return sum;
+}
+
 struct Work {
   unsigned long long* key[2];
   int* idx[2];
@@ -106,6 +127,11 @@ blink_status validate_problem(const blink_problem* p, int call) {
   if (p->cols_per_wg != 0 && p->cols_per_wg != 2 && p->cols_per_wg != 4 && p->cols_per_wg != 8)
     return BLINK_E_ARG;
   if (p->rows_wg < 0) return BLINK_E_ARG;
+  if (p->kernel_support < 0 || p->kernel_support > KB_MAX_SUPPORT) return BLINK_E_ARG;
+  if (p->kernel_support > 0) {
+    if (!isfinite(p->kernel_beta)) return BLINK_E_ARG;
+    if (p->kernel_beta < 0 && kb_default_beta(p->kernel_support) < 0) return BLINK_E_ARG;
+  }
   if (call < BLINK_CALL_GRID || call > BLINK_CALL_ADJOINT) return BLINK_E_ARG;
   if (p->grid_n < 2 || (p->grid_n & 1)) return BLINK_E_SIZE;
   if (call != BLINK_CALL_GRID) {
@@ -116,6 +142,8 @@ blink_status validate_problem(const blink_problem* p, int call) {
   if ((double)T * C * B > 9.0e18 || (double)T * C * N * N > 9.0e18) return BLINK_E_SIZE;
   if (!n_supported(p->grid_n)) return BLINK_E_UNSUPPORTED;
   if (call == BLINK_CALL_ADJOINT && p->vis_type != BLINK_VIS_C64) return BLINK_E_UNSUPPORTED;
+  if (p->kernel_support > 0 && (p->weighting != BLINK_NATURAL || call == BLINK_CALL_ADJOINT))
+    return BLINK_E_UNSUPPORTED;
   return BLINK_OK;
 }
 
@@ -247,6 +275,13 @@ ImgArgs make_args(const blink_problem* p, const blink_inputs* in, const Work& w)
   a.n_unflagged = w.counters; a.n_valid = w.counters + p->n_time;
   a.bnd = w.bnd; a.ncz = w.ncz; a.wpart = w.wpart; a.kpart = w.kpart; a.wstride = w.wstride;
   a.half = w.half; a.gamma = w.gamma; a.pacc = w.pacc;
+  a.kw = p->kernel_support;
+  if (a.kw > 0) {
+    const double beta = p->kernel_beta < 0 ? kb_default_beta(a.kw) : p->kernel_beta;
+    a.kbeta = (float)beta;
+    a.kinv = (float)(1.0 / bessel_i0(beta));
+    a.ktaper0 = (float)(beta > 0 ? sinh(beta) / beta : 1.0);
+  }
   return a;
 }
 
@@ -279,8 +314,12 @@ blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t s
   Timer& T_ = *tm;
   const long long n_img = (long long)p->n_time * p->n_chan;
   const bool uni = p->weighting == BLINK_UNIFORM;
-  const int cpw = p->cols_per_wg ? p->cols_per_wg : cols_per_wg(N);
+  const bool kb = p->kernel_support > 0;
+  // kernel gridding runs at the default tile width only
+  const int cpw = kb ? cols_per_wg(N) : (p->cols_per_wg ? p->cols_per_wg : cols_per_wg(N));
   if (cols_lds<N>(cpw, uni) > LDS_PER_CU) return BLINK_E_UNSUPPORTED;
+  const size_t rows_lds = Rows<N>::LDS + (kb ? (size_t)p->out_n * sizeof(float) : 0);
+  if (rows_lds > LDS_PER_CU) return BLINK_E_UNSUPPORTED;
   a.wtiles = (int)cdiv(N / 2, cpw);
   T_.begin(1);
   hipLaunchKernelGGL(k_bounds, dim3((unsigned)n_img), dim3(256), 0, st, a);
@@ -289,8 +328,18 @@ blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t s
     const int n = (int)std::min<long long>(chunk, n_img - i0);
     a.img0 = (int)i0; a.nimg = n;
     T_.begin(2);
-    if (uni) launch_cols_image<N, true>(a, n, cpw, st);
-    else launch_cols_image<N, false>(a, n, cpw, st);
+    if (kb) {
+      constexpr int CPW = cols_per_wg(N);
+      using C_ = Cols<N, CPW>;
+      a.ntiles = (int)cdiv(N / 2, CPW);
+      const dim3 g1((unsigned)(cdiv(n, 8) * 8LL * a.ntiles));
+      hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, false, CPW, true>), g1, dim3(C_::THREADS),
+                         C_::lds_bytes(false), st, a);
+    } else if (uni) {
+      launch_cols_image<N, true>(a, n, cpw, st);
+    } else {
+      launch_cols_image<N, false>(a, n, cpw, st);
+    }
     T_.end();
     // row pass: one workgroup per row tile, or a persistent grid of rows_wg workgroups
     const long long row_tiles = (long long)n * cdiv(p->out_n / 2, Rows<N>::PPW);
@@ -298,11 +347,11 @@ blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t s
     T_.begin(3);
     if constexpr (blocks_aligned(N)) {
       if ((p->out_n / 2) % WAVE == 0)
-        hipLaunchKernelGGL((k_rows<N, true>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), Rows<N>::LDS, st, a);
+        hipLaunchKernelGGL((k_rows<N, true>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), rows_lds, st, a);
       else
-        hipLaunchKernelGGL((k_rows<N, false>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), Rows<N>::LDS, st, a);
+        hipLaunchKernelGGL((k_rows<N, false>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), rows_lds, st, a);
     } else {
-      hipLaunchKernelGGL((k_rows<N, false>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), Rows<N>::LDS, st, a);
+      hipLaunchKernelGGL((k_rows<N, false>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), rows_lds, st, a);
     }
     T_.end();
   }
@@ -321,7 +370,10 @@ blink_status grid_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t st
     a.img0 = (int)i0; a.nimg = n;
     a.ntiles = (int)cdiv(N, Cols<N>::CPW);
     const dim3 g1((unsigned)(cdiv(n, 8) * 8LL * a.ntiles));
-    if (uni)
+    if (p->kernel_support > 0)
+      hipLaunchKernelGGL((k_grid_cols<N, MODE_GRID, false, Cols<N>::CPW, true>), g1, dim3(Cols<N>::THREADS),
+                         lds1, st, a);
+    else if (uni)
       hipLaunchKernelGGL((k_grid_cols<N, MODE_GRID, true>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
     else
       hipLaunchKernelGGL((k_grid_cols<N, MODE_GRID, false>), g1, dim3(Cols<N>::THREADS), lds1, st, a);

@@ -264,6 +264,11 @@ struct ImgArgs {
   float2* pacc;                 // [B] sum over images of gamma conj(V)
   float2* gain_grad;            // [A]
   int n_ant;
+  // Kaiser-Bessel gridding kernel (kw = support in cells, 0 = nearest cell)
+  int kw;
+  float kbeta;                  // shape
+  float kinv;                   // 1 / I0(kbeta)
+  float ktaper0;                // sinh(kbeta) / kbeta: the correction's value at 0 before normalising
 };
 
 // bnd[c + N/2] = first sorted position j with clamp(rint(u_j s)) >= c for
@@ -303,8 +308,10 @@ __global__ void __launch_bounds__(256) k_bounds(ImgArgs a) {
     }
     for (int c = clast + 1 + (int)threadIdx.x; c <= H + 1; c += blockDim.x) bnd[c + H] = nv;
   }
-  // every entry lies in a column |c| <= max(|first|, |last|) of the sorted order
-  if (threadIdx.x == 0) a.ncz[img] = nv == 0 ? 0 : min(H, max(clast, -col(0)) + 1);
+  // every entry lies in a column |c| <= max(|first|, |last|) of the sorted order;
+  // a gridding kernel reaches at most W/2 + 1 columns further
+  const int reach = a.kw > 0 ? a.kw / 2 + 1 : 0;
+  if (threadIdx.x == 0) a.ncz[img] = nv == 0 ? 0 : min(H, max(clast, -col(0)) + 1 + reach);
 }
 
 // Sum of the per-tile partials of one image (read by one wavefront; every
@@ -312,6 +319,14 @@ __global__ void __launch_bounds__(256) k_bounds(ImgArgs a) {
 __device__ __forceinline__ int sum_partials(const int* part, int img, int wstride, int wtiles, int lane) {
   int v = 0;
   for (int i = lane; i < wtiles; i += WAVE) v += part[(size_t)img * wstride + i];
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// The same for partials holding FP32 weight sums (kernel gridding).
+__device__ __forceinline__ float sum_partials_f(const int* part, int img, int wstride, int wtiles, int lane) {
+  float v = 0.f;
+  for (int i = lane; i < wtiles; i += WAVE) v += __int_as_float(part[(size_t)img * wstride + i]);
   for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
@@ -434,6 +449,81 @@ __device__ __forceinline__ void grid_steps(const ImgArgs& a, const ColSpan& c, i
   }
 }
 
+// ------------------------------------------------------------- kernel gridding
+// Kaiser-Bessel weight C(d) = I0(beta sqrt(1 - (2d/W)^2)) / I0(beta), |d| <= W/2.
+__device__ __forceinline__ float kb_weight(float d, const ImgArgs& a) {
+  const float t = 2.0f * d / (float)a.kw;
+  return cyl_bessel_i0f(a.kbeta * sqrtf(fmaxf(0.0f, 1.0f - t * t))) * a.kinv;
+}
+
+// Normalised transform of the continuous kernel at xi cycles per cell:
+// [sinh(z)/z] / [sinh(beta)/beta], z = sqrt(beta^2 - (pi W xi)^2) (sin(|z|)/|z|
+// beyond pi W |xi| = beta).
+__device__ __forceinline__ double kb_taper(double xi, const ImgArgs& a) {
+  const double x = M_PI * (double)a.kw * xi;
+  const double b = (double)a.kbeta;
+  const double z2 = b * b - x * x;
+  double f = 1.0;
+  if (z2 > 0.0) { const double z = sqrt(z2); f = sinh(z) / z; }
+  else if (z2 < 0.0) { const double z = sqrt(-z2); f = sin(z) / z; }
+  return f / (double)a.ktaper0;
+}
+
+// Kernel gridding of u-cell column c: the span holds the sorted entries whose
+// nearest column lies within W/2 + 1 of c (direct) and of -c (mirror). Each
+// direct entry at exact position x adds C(c - x_u) C(j - x_v) V' to the rows j
+// of its footprint, each mirror entry (its conjugate, at -x) adds
+// C(c + x_u) C(j + x_v) conj(V'). One entry per lane per step; within a step
+// the footprint rows are added in sequence, lanes in LDS order, so the order
+// of the adds is fixed. kd / kc count kept entries whose nearest column is c
+// (each baseline once); wsum collects this lane's weights.
+template <int N, bool COUNT>
+__device__ __forceinline__ void grid_steps_kb(const ImgArgs& a, const ColSpan& sp, int c, float2* buf,
+                                              int* cnt, int t, int ch, double s, int lane, int& kd,
+                                              int& kc, float& wsum) {
+  constexpr int H = N / 2;
+  const size_t tb = (size_t)t * a.B;
+  const size_t vb = ((size_t)t * a.C + ch) * a.B;
+  const double hw = 0.5 * a.kw;
+  const int nd = sp.nd(), total = sp.total();
+  for (int i0 = 0; i0 < total; i0 += WAVE) {
+    const int i = i0 + lane;
+    bool ok = i < total;
+    const bool cj = i >= nd;
+    const int j = cj ? sp.clo + (i - nd) : sp.dlo + i;
+    double xu = 0.0, xv = 0.0;
+    int b = 0;
+    if (ok) {
+      xu = a.su[tb + j] * s;
+      xv = a.sv[tb + j] * s;
+      b = a.perm[tb + j];
+    }
+    // kept iff the whole footprint lies inside |i| < N/2 on both axes
+    ok = ok && ceil(xu - hw) > (double)-H && floor(xu + hw) < (double)H &&
+         ceil(xv - hw) > (double)-H && floor(xv + hw) < (double)H;
+    if (cj) { xu = -xu; xv = -xv; }
+    const bool home = ok && rint(xu) == (double)c;
+    kd += __popcll(__ballot(home && !cj));
+    kc += __popcll(__ballot(home && cj));
+    const double du = (double)c - xu;
+    if (ok && fabs(du) <= hw) {
+      float2 v = load_vis(a, vb + b, b, ch);
+      if (cj) v.y = -v.y;
+      const float wu = kb_weight((float)du, a);
+      const int j0 = (int)ceil(xv - hw), j1 = (int)floor(xv + hw);
+      for (int r = j0; r <= j1; ++r) {
+        const float w = wu * kb_weight((float)((double)r - xv), a);
+        const int row = r < 0 ? r + N : r;
+        float2* p = &buf[pad(row)];
+        atomicAdd(&p->x, w * v.x);
+        atomicAdd(&p->y, w * v.y);
+        if (COUNT) atomicAdd(&cnt[row], 1);
+        wsum += w;
+      }
+    }
+  }
+}
+
 // u-cell columns (one wavefront each) per workgroup of the column kernels
 __host__ __device__ constexpr int cols_per_wg(int n) { return n <= 1024 ? 8 : (n <= 2048 ? 4 : 2); }
 
@@ -472,8 +562,10 @@ struct Cols {
 // The 1D grid is laid out so that all column tiles of an image share one XCD
 // (workgroup L runs on XCD L mod 8): the image's visibility row and the
 // timestep's sorted lists are then fetched into a single L2.
-template <int N, int MODE, bool UNI, int CPW = cols_per_wg(N)>
+// KB: Kaiser-Bessel kernel gridding (natural weighting) instead of nearest cell.
+template <int N, int MODE, bool UNI, int CPW = cols_per_wg(N), bool KB = false>
 __global__ void __launch_bounds__((Cols<N, CPW>::THREADS)) k_grid_cols(ImgArgs a) {
+  static_assert(!(KB && UNI), "kernel gridding is natural-weighting only");
   extern __shared__ float4 lds_raw[];
   __shared__ int red[2 * CPW];
   using C_ = Cols<N, CPW>;
@@ -513,7 +605,19 @@ __global__ void __launch_bounds__((Cols<N, CPW>::THREADS)) k_grid_cols(ImgArgs a
   wave_sync();
 
   int kept_b = 0, wcontrib = 0;
-  if (active && cs != H && cs != -H) {
+  if (KB && active && cs != H && cs != -H) {
+    const int* bnd = a.bnd + (size_t)img * (N + 2);
+    const int hk = a.kw / 2 + 1;
+    auto at = [&](int c) { return bnd[min(max(c, -H), H + 1) + H]; };
+    const ColSpan span{at(cs - hk), at(cs + hk + 1), at(-cs - hk), at(-cs + hk + 1)};
+    int kd = 0, kc = 0;
+    float ws = 0.f;
+    grid_steps_kb<N, CNT>(a, span, cs, buf, cnt, t, ch, s, lane, kd, kc, ws);
+    wave_sync();
+    kept_b = kd + ((MODE == MODE_IMAGE && cs > 0) ? kc : 0);
+    for (int o = WAVE / 2; o > 0; o >>= 1) ws += __shfl_xor(ws, o);
+    wcontrib = __float_as_int(((MODE == MODE_IMAGE && cs > 0) ? 2.0f : 1.0f) * ws);
+  } else if (!KB && active && cs != H && cs != -H) {
     const int* bnd = a.bnd + (size_t)img * (N + 2);
     const ColSpan span{bnd[cs + H], bnd[cs + 1 + H], bnd[-cs + H], bnd[-cs + 1 + H]};
     int kd = 0, kc = 0;
@@ -546,8 +650,13 @@ __global__ void __launch_bounds__((Cols<N, CPW>::THREADS)) k_grid_cols(ImgArgs a
   __syncthreads();                                   // also publishes the LDS twiddles
   if (threadIdx.x == 0) {
     int ws = 0, ks = 0;
-    for (int i = 0; i < CPW; ++i) { ws += red[i]; ks += red[CPW + i]; }
-    a.wpart[(size_t)img * a.wstride + tile] = ws;
+    float wf = 0.f;                                  // kernel gridding: FP32 weight sums
+    for (int i = 0; i < CPW; ++i) {
+      ws += red[i];
+      wf += __int_as_float(red[i]);
+      ks += red[CPW + i];
+    }
+    a.wpart[(size_t)img * a.wstride + tile] = KB ? __float_as_int(wf) : ws;
     a.kpart[(size_t)img * a.wstride + tile] = ks;
   }
 
@@ -580,11 +689,13 @@ __global__ void k_grid_finish(ImgArgs a, int n_img) {
   if (img >= n_img) return;
   const int t = img / a.C;
   int w = 0, k = 0;
+  float wf = 0.f;                                    // kernel gridding: FP32 weight sums
   for (int i = 0; i < a.wtiles; ++i) {
     w += a.wpart[(size_t)img * a.wstride + i];
+    wf += __int_as_float(a.wpart[(size_t)img * a.wstride + i]);
     k += a.kpart[(size_t)img * a.wstride + i];
   }
-  if (a.weight_sum) a.weight_sum[img] = (float)w;
+  if (a.weight_sum) a.weight_sum[img] = a.kw > 0 ? wf : (float)w;
   if (a.n_dropped) a.n_dropped[img] = a.n_unflagged[t] - k;
 }
 
@@ -632,6 +743,12 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
   const int ntr = (npair + PPW - 1) / PPW;           // row tiles per image
   const int total = a.nimg * ntr;
   const float2* tw = stage_twiddles<N>(lds + PPW * ST);
+  // kernel gridding: 1 / c((l - M/2) / N) per image column, published by the
+  // first barrier of the loop
+  float* lcorr = reinterpret_cast<float*>(lds + PPW * ST + Rows<N>::TW);
+  const bool kbon = a.kw > 0;
+  if (kbon)
+    for (int l = threadIdx.x; l < a.M; l += THR) lcorr[l] = (float)(1.0 / kb_taper((double)(l - a.M / 2) / N, a));
 
   // thread t always serves pair slot t % PPW and columns t / PPW + i * (THR / PPW)
   const int kt = threadIdx.x / PPW, pt = threadIdx.x % PPW;
@@ -656,9 +773,10 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
     asm volatile("" : "+v"(lane_i), "+v"(ln));
     const int li = tile / ntr, p0 = (tile % ntr) * PPW;
     const int img = a.img0 + li;
-    const int W = sum_partials(a.wpart, img, a.wstride, a.wtiles, lane_i);
-    const float scale = a.norm ? (W > 0 ? 1.0f / (float)W : 0.0f) : 1.0f;
-    if (p0 == 0 && ln == 0 && a.weight_sum) a.weight_sum[img] = (float)W;
+    const float W = kbon ? sum_partials_f(a.wpart, img, a.wstride, a.wtiles, lane_i)
+                         : (float)sum_partials(a.wpart, img, a.wstride, a.wtiles, lane_i);
+    const float scale = a.norm ? (W > 0 ? 1.0f / W : 0.0f) : 1.0f;
+    if (p0 == 0 && ln == 0 && a.weight_sum) a.weight_sum[img] = W;
     const int kti = ln / PPW, pti = ln % PPW;
     __syncthreads();                                  // previous tile's rows have left LDS
     auto put = [&](int i, float4 ab) {
@@ -689,14 +807,20 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
       float2* z = lds + wave * ST;
       float* r0 = a.images + ((size_t)img * M + 2 * pair) * M;
       float* r1 = r0 + M;
+      float s0 = scale, s1 = scale;
+      if (kbon) {
+        s0 *= (float)(1.0 / kb_taper((double)(2 * pair - M / 2) / N, a));
+        s1 *= (float)(1.0 / kb_taper((double)(2 * pair + 1 - M / 2) / N, a));
+      }
       int hm = M / 2;
       asm volatile("" : "+s"(hm));   // block tests stay inside the loop (hoisted they spill)
       // image columns of the cutout straight from the last stage: column l
       // holds u-frequency q = (l - M/2) mod N; row 2p is Re z, row 2p+1 is Im z
       wave_fft_emit<N, +1>(z, lane_i, tw, [&](auto qb, float2 v) {
         auto st = [&](unsigned l) {
-          store_at(r0, l, v.x * scale);
-          store_at(r1, l, v.y * scale);
+          const float cl = kbon ? lcorr[l] : 1.0f;
+          store_at(r0, l, v.x * s0 * cl);
+          store_at(r1, l, v.y * s1 * cl);
         };
         if constexpr (AL) cutout_block_aligned<N, decltype(qb)::value>(lane_i, hm, st);
         else cutout_lane<N, decltype(qb)::value>(lane_i, hm, st);

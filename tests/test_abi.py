@@ -78,6 +78,11 @@ def _image(lib, p, inp, images=FAKE, ws=None, nbytes=0):
     (dict(weighting=2), E_ARG), (dict(norm=5), E_ARG), (dict(vis_type=3), E_ARG),
     (dict(chunk_images=-2), E_ARG), (dict(cols_per_wg=3), E_ARG), (dict(cols_per_wg=16), E_ARG),
     (dict(rows_wg=-1), E_ARG),
+    (dict(kernel_support=-1), E_ARG), (dict(kernel_support=17), E_ARG),
+    (dict(kernel_support=1, kernel_beta=-1.0), E_ARG),        # default shape needs W >= 2
+    (dict(kernel_support=4, kernel_beta=float("nan")), E_ARG),
+    (dict(kernel_support=4, kernel_beta=float("inf")), E_ARG),
+    (dict(kernel_support=4, kernel_beta=-1.0, weighting=1), E_UNSUP),   # natural weighting only
 ])
 def test_problem_validation(lib, kw, code):
     assert _image(lib, _prob(**kw), _inputs()) == code
@@ -155,3 +160,12 @@ def test_workspace_sizes_scale(lib):
     c3.chunk_images = 8
     s8 = lib.blink_workspace_size(ctypes.byref(c3), 1)
     assert s8 - s4 >= 4 * 512 * 512 * 8
+
+
+def test_kernel_gridding_has_no_adjoint(lib):
+    p = _prob(kernel_support=6, kernel_beta=-1.0)
+    a = lib.blink_degrid_adjoint
+    assert a(ctypes.byref(p), ctypes.byref(_inputs()), FAKE, FAKE, None, None, 0, None) == E_UNSUP
+    # the same problem without the kernel passes validation (and then needs a workspace)
+    p0 = _prob()
+    assert a(ctypes.byref(p0), ctypes.byref(_inputs()), FAKE, FAKE, None, None, 0, None) == E_WS
