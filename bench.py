@@ -26,6 +26,7 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
+KB_SUPPORT = 6                 # Kaiser-Bessel support (cells) of the kernel-gridding workload
 METRIC = "dirty images/s and visibilities/s at 128 tiles, 1024² grid; % HBM roofline"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_grid_cols_rows_widefield1024.json")
 CSRC = os.path.join(ROOT, "paper_2405_13478_amd", "csrc")
@@ -67,18 +68,20 @@ def nonzero_columns(w, t_slice):
 def _oracle_one(job):
     """One image with the FP64 oracle (runs in a worker process)."""
     import oracle
-    vis, u, v, f, n, dx, m, wt, nm = job
+    vis, u, v, f, n, dx, m, wt, nm, ksup = job
+    if ksup > 0:
+        return oracle.kernel_gridding.image_one_conv(vis, u, v, f, n, dx, m, nm, ksup)["image"].shape[0]
     return oracle.image_one(vis, u, v, f, n, dx, m, wt, nm)["image"].shape[0]
 
 
-def cpu_baseline(w, vis_cpu, sample, cores):
+def cpu_baseline(w, vis_cpu, sample, cores, ksup=0):
     import multiprocessing as mp
     ctx = mp.get_context("spawn")
     jobs = []
     for i in sample:
         t, c = divmod(i, w.n_chan)
         jobs.append((vis_cpu[t, c], w.uvw_m[t, :, 0], w.uvw_m[t, :, 1], float(w.freq_hz[c]),
-                     w.grid_n, w.pixscale, w.out_n, w.weighting, w.norm))
+                     w.grid_n, w.pixscale, w.out_n, w.weighting, w.norm, ksup))
     env_keep = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
     for k in env_keep:
         os.environ[k] = "1"
@@ -203,7 +206,7 @@ def summarize(out_dir):
 def _setup(args, synth):
     """(workload, timesteps per step, channels per step) for --workload."""
     k = args.workload
-    if k == "widefield":
+    if k in ("widefield", "widefield_kb"):
         TT = args.timesteps_per_step or 10
         return synth.widefield(n_time=max(TT, args.timesteps or 100), n_chan=768), TT
     if k == "plain":
@@ -219,6 +222,7 @@ def _setup(args, synth):
 
 DESCRIPTION = {
     "widefield": "widefield 128 tiles (8128 baselines), 768 ch x 100 timesteps, 1024^2 grid -> 512^2 cutout, natural weighting",
+    "widefield_kb": "widefield 128 tiles (8128 baselines), 768 ch x 100 timesteps, 1024^2 grid -> 512^2 cutout, natural weighting, Kaiser-Bessel gridding kernel of 6 cells with taper correction",
     "plain": "plain single image, 32 antennas (496 baselines), 1 ch at 160 MHz, 128^2, natural weighting",
     "allsky": "station all-sky, 256 antennas (32640 baselines), 32 ch x 1000 timesteps (32,000 images), 180^2, uniform weighting, 2-10% flagged per timestep",
     "precision": "precision, 256 tiles in 5 km (32640 baselines), 384 ch x 50 timesteps, 2048^2, uniform weighting",
@@ -277,6 +281,7 @@ def bench_images(args, np, torch, blink, synth, dev):
     t_gen = time.perf_counter() - t_gen
     n_img = TT * w.n_chan
     M, N, H, B = w.out_n, w.grid_n, w.grid_n // 2, w.n_bl
+    ksup = KB_SUPPORT if args.workload == "widefield_kb" else 0
     images = torch.empty((n_img, M, M), dtype=torch.float32, device=dev)   # reused per step
     ws_cache = {}
 
@@ -288,7 +293,7 @@ def bench_images(args, np, torch, blink, synth, dev):
                                      args.cols_per_wg, args.rows_wg)
         tunings[vbytes] = tun
         p = blink.blink.make_problem(v[:TT], uvw[:TT], freq, N, w.pixscale, M, w.weighting, w.norm,
-                                     None, **tun)
+                                     None, **tun, kernel_support=ksup)
         ws_cache[vbytes] = ws = blink.workspace(p, blink.CALL_IMAGE, dev)
 
         def run(k, tm):
@@ -296,13 +301,15 @@ def bench_images(args, np, torch, blink, synth, dev):
             sl = slice(b * TT, (b + 1) * TT)
             blink.image_batch(v[sl], uvw[sl], freq, grid_n=N, pixscale=w.pixscale, out_n=M,
                               weighting=w.weighting, norm=w.norm, flags=None if flags is None else flags[sl],
-                              vis_scale=scale, images=images, ws=ws, times=tm, **tun)
+                              vis_scale=scale, images=images, ws=ws, times=tm, **tun, kernel_support=ksup)
         return run
 
     ncz = np.concatenate([nonzero_columns(w, slice(b * TT, (b + 1) * TT))
                           for b in range(min(args.steps, n_batches))])
     unflagged = (B if w.flags is None else
                  float(np.mean([(w.flags[t] == 0).sum() for t in range(min(args.steps, n_batches) * TT)])))
+    if ksup:   # a kernel reaches up to W/2 + 1 columns beyond the outermost baseline
+        ncz = np.minimum(ncz + ksup // 2 + 1, H)
     ncz_mean = float(ncz.mean())
 
     def measure(v, scale, vbytes):
@@ -394,7 +401,7 @@ def bench_images(args, np, torch, blink, synth, dev):
     if args.workload == "plain":
         out["latency_us_per_image"] = round(res["ms_per_step"] * 1e3, 2)
 
-    sample_n = args.cpu_sample if args.cpu_sample is not None else {"widefield": 128, "plain": 64, "allsky": 4096, "precision": 16}[args.workload]
+    sample_n = args.cpu_sample if args.cpu_sample is not None else {"widefield": 128, "widefield_kb": 32, "plain": 64, "allsky": 4096, "precision": 16}[args.workload]
     if not args.no_cpu_baseline and sample_n > 0:
         cores = max(1, min(16, os.cpu_count() or 1))
         S = min(sample_n, w.n_img)
@@ -402,7 +409,7 @@ def bench_images(args, np, torch, blink, synth, dev):
         sample = [(k * stride) % w.n_chan + ((k * stride) // w.n_chan) * w.n_chan for k in range(S)]
         tmax = max(sample) // w.n_chan + 1
         vis_cpu = vis[:tmax].cpu().numpy()
-        rate, dt = cpu_baseline(w, vis_cpu, sample, cores)
+        rate, dt = cpu_baseline(w, vis_cpu, sample, cores, ksup)
         out["cpu_baseline"] = {"value": round(rate, 3), "unit": "images/s", "cores": cores, "kind": "oracle",
                                "sample": f"{S} images (timesteps < {tmax}, channels every {stride}) of the same "
                                          f"workload, FP64 numpy oracle, {cores}-process pool, {dt:.1f} s wall"}
@@ -471,7 +478,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="widefield",
-                    choices=("widefield", "plain", "allsky", "diff", "precision"))
+                    choices=("widefield", "widefield_kb", "plain", "allsky", "diff", "precision"))
     ap.add_argument("--timesteps-per-step", type=int, default=None)
     ap.add_argument("--timesteps", type=int, default=None,
                     help="timesteps of the job generated into HBM (default: the whole widefield job)")
@@ -494,7 +501,8 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "images shard across GPUs with no exchange, see DESIGN.md", file=sys.stderr)
         sys.exit(2)
-    defaults = {"widefield": (20, 3), "plain": (500, 20), "allsky": (3, 1), "diff": (5, 2), "precision": (5, 1)}
+    defaults = {"widefield": (20, 3), "widefield_kb": (10, 2), "plain": (500, 20), "allsky": (3, 1),
+                "diff": (5, 2), "precision": (5, 1)}
     ds, dw = defaults[args.workload]
     args.steps = ds if args.steps is None else args.steps
     args.warmup = dw if args.warmup is None else args.warmup

@@ -309,6 +309,19 @@ size_t cols_lds(int cpw, bool uni) {
 }
 constexpr size_t LDS_PER_CU = size_t(160) << 10;
 
+// Row pass: the block-store variant when the cutout half-width is a
+// multiple of the wavefront width (and the plan's last stage allows it).
+template <int N, bool KB>
+void launch_rows(const blink_problem* p, ImgArgs& a, long long nwg, size_t lds, hipStream_t st) {
+  if constexpr (blocks_aligned(N)) {
+    if ((p->out_n / 2) % WAVE == 0) {
+      hipLaunchKernelGGL((k_rows<N, true, KB>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), lds, st, a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_rows<N, false, KB>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), lds, st, a);
+}
+
 template <int N>
 blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t st, Timer* tm) {
   Timer& T_ = *tm;
@@ -345,14 +358,8 @@ blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t s
     const long long row_tiles = (long long)n * cdiv(p->out_n / 2, Rows<N>::PPW);
     const long long nwg = p->rows_wg > 0 ? std::min<long long>(row_tiles, p->rows_wg) : row_tiles;
     T_.begin(3);
-    if constexpr (blocks_aligned(N)) {
-      if ((p->out_n / 2) % WAVE == 0)
-        hipLaunchKernelGGL((k_rows<N, true>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), rows_lds, st, a);
-      else
-        hipLaunchKernelGGL((k_rows<N, false>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), rows_lds, st, a);
-    } else {
-      hipLaunchKernelGGL((k_rows<N, false>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), rows_lds, st, a);
-    }
+    if (kb) launch_rows<N, true>(p, a, nwg, rows_lds, st);
+    else launch_rows<N, false>(p, a, nwg, rows_lds, st);
     T_.end();
   }
   return launched();

@@ -459,14 +459,13 @@ __device__ __forceinline__ float kb_weight(float d, const ImgArgs& a) {
 // Normalised transform of the continuous kernel at xi cycles per cell:
 // [sinh(z)/z] / [sinh(beta)/beta], z = sqrt(beta^2 - (pi W xi)^2) (sin(|z|)/|z|
 // beyond pi W |xi| = beta).
-__device__ __forceinline__ double kb_taper(double xi, const ImgArgs& a) {
-  const double x = M_PI * (double)a.kw * xi;
-  const double b = (double)a.kbeta;
-  const double z2 = b * b - x * x;
-  double f = 1.0;
-  if (z2 > 0.0) { const double z = sqrt(z2); f = sinh(z) / z; }
-  else if (z2 < 0.0) { const double z = sqrt(-z2); f = sin(z) / z; }
-  return f / (double)a.ktaper0;
+__device__ __forceinline__ float kb_taper(float xi, const ImgArgs& a) {
+  const float x = 3.14159265358979f * (float)a.kw * xi;
+  const float z2 = a.kbeta * a.kbeta - x * x;
+  float f = 1.0f;
+  if (z2 > 0.0f) { const float z = sqrtf(z2); f = sinhf(z) / z; }
+  else if (z2 < 0.0f) { const float z = sqrtf(-z2); f = sinf(z) / z; }
+  return f / a.ktaper0;
 }
 
 // Kernel gridding of u-cell column c: the span holds the sorted entries whose
@@ -725,7 +724,9 @@ struct Rows {
 // AL: the cutout half-width M/2 is a multiple of the wavefront width and the
 // plan's last-stage blocks are aligned (blocks_aligned), so each block of 64
 // output columns is stored or skipped whole.
-template <int N, bool AL>
+// KB: the image was gridded with the Kaiser-Bessel kernel; the stores apply
+// its correction.
+template <int N, bool AL, bool KB>
 __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
   static_assert(!AL || blocks_aligned(N), "aligned cutout needs aligned blocks");
   extern __shared__ float4 lds_raw[];
@@ -743,12 +744,13 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
   const int ntr = (npair + PPW - 1) / PPW;           // row tiles per image
   const int total = a.nimg * ntr;
   const float2* tw = stage_twiddles<N>(lds + PPW * ST);
-  // kernel gridding: 1 / c((l - M/2) / N) per image column, published by the
-  // first barrier of the loop
+  // kernel gridding: 1 / c((l - M/2) / N) per image column l (the same table
+  // serves the rows: the correction is separable), published by the first
+  // barrier of the loop
   float* lcorr = reinterpret_cast<float*>(lds + PPW * ST + Rows<N>::TW);
-  const bool kbon = a.kw > 0;
+  constexpr bool kbon = KB;
   if (kbon)
-    for (int l = threadIdx.x; l < a.M; l += THR) lcorr[l] = (float)(1.0 / kb_taper((double)(l - a.M / 2) / N, a));
+    for (int l = threadIdx.x; l < a.M; l += THR) lcorr[l] = 1.0f / kb_taper((float)(l - a.M / 2) / N, a);
 
   // thread t always serves pair slot t % PPW and columns t / PPW + i * (THR / PPW)
   const int kt = threadIdx.x / PPW, pt = threadIdx.x % PPW;
@@ -809,8 +811,8 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
       float* r1 = r0 + M;
       float s0 = scale, s1 = scale;
       if (kbon) {
-        s0 *= (float)(1.0 / kb_taper((double)(2 * pair - M / 2) / N, a));
-        s1 *= (float)(1.0 / kb_taper((double)(2 * pair + 1 - M / 2) / N, a));
+        s0 *= lcorr[2 * pair];
+        s1 *= lcorr[2 * pair + 1];
       }
       int hm = M / 2;
       asm volatile("" : "+s"(hm));   // block tests stay inside the loop (hoisted they spill)
