@@ -10,3 +10,4 @@ from .blink_oracle import (C_LIGHT, NATURAL, UNIFORM, NORM_NONE, NORM_WEIGHTS,  
                            shift_real_cut, image_one, image_batch, direct_image,
                            adjoint_one, adjoint_batch, fft_flops_estimate)
 from . import kernel_gridding  # noqa: F401,E402
+from . import dynamic_spectra  # noqa: F401,E402
