@@ -471,6 +471,65 @@ def bench_diff(args, np, torch, blink, synth, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_dynspec(args, np, torch, blink, synth, dev):
+    """Dynamic spectra of a cube of widefield dirty images, mean of 8 preceding images subtracted."""
+    T, C, K = 100, 96, 8
+    w = synth.widefield(n_time=T, n_chan=C, chan_stride=8)
+    vis = synth.visibilities(w, device=dev)
+    M = w.out_n
+    cube = blink.image_batch(vis, torch.from_numpy(w.uvw_m).to(dev), torch.from_numpy(w.freq_hz).to(dev),
+                             grid_n=w.grid_n, pixscale=w.pixscale, out_n=M, weighting=w.weighting,
+                             norm=w.norm).view(T, C, M, M)
+    del vis
+    out = torch.empty((M * M, C, T), dtype=torch.float32, device=dev)
+    for _ in range(args.warmup):
+        blink.dynamic_spectra(cube, blink.REF_MEAN, K, out=out)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()       # the library launches on the caller's current stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(args.steps):
+        blink.dynamic_spectra(cube, blink.REF_MEAN, K, out=out)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    # the plain transposition (no reference) on the same cube, for comparison
+    e0.record(st)
+    for _ in range(args.steps):
+        blink.dynamic_spectra(cube, blink.REF_NONE, out=out)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms_none = e0.elapsed_time(e1) / args.steps
+    n_img = T * C
+    alg = 2.0 * n_img * M * M * 4                 # every pixel read once and written once
+    achieved = alg / (ms * 1e-3) / 1e9
+    out_line = {
+        "metric": "dirty images/s (dynspec)", "value": round(n_img / (ms / 1e3), 1), "unit": "images/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 (f64 window sums)",
+        "data": "synthetic",
+        "config": {"workload": f"dynamic spectra of {T} timesteps x {C} channels of 512^2 widefield dirty "
+                               f"images ({alg / 2e9:.1f} GB), mean of the {K} preceding images subtracted",
+                   "images_per_step": n_img, "out_n": M, "ref_len": K},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "dynspec",
+                     "mean_launch_ms": round(ms, 5), "algorithmic_bytes_per_launch": int(alg),
+                     "images_per_launch": n_img},
+        "transpose_only_ms_per_step": round(ms_none, 4),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        sub = cube[:, :4].cpu().numpy()
+        t0 = time.perf_counter()
+        oracle.dynamic_spectra.dynamic_spectra(sub, 1, K)
+        dt = time.perf_counter() - t0
+        out_line["cpu_baseline"] = {"value": round(T * 4 / dt, 3), "unit": "images/s", "cores": 1,
+                                    "kind": "oracle",
+                                    "sample": f"{T} timesteps x 4 channels of the same cube (numpy, one thread), "
+                                              f"{dt:.1f} s"}
+    print(json.dumps(out_line), flush=True)
+
+
 # ---------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -478,7 +537,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="widefield",
-                    choices=("widefield", "widefield_kb", "plain", "allsky", "diff", "precision"))
+                    choices=("widefield", "widefield_kb", "plain", "allsky", "diff", "precision", "dynspec"))
     ap.add_argument("--timesteps-per-step", type=int, default=None)
     ap.add_argument("--timesteps", type=int, default=None,
                     help="timesteps of the job generated into HBM (default: the whole widefield job)")
@@ -502,7 +561,7 @@ def main():
               "images shard across GPUs with no exchange, see DESIGN.md", file=sys.stderr)
         sys.exit(2)
     defaults = {"widefield": (20, 3), "widefield_kb": (10, 2), "plain": (500, 20), "allsky": (3, 1),
-                "diff": (5, 2), "precision": (5, 1)}
+                "diff": (5, 2), "precision": (5, 1), "dynspec": (10, 2)}
     ds, dw = defaults[args.workload]
     args.steps = ds if args.steps is None else args.steps
     args.warmup = dw if args.warmup is None else args.warmup
@@ -525,6 +584,8 @@ def main():
     blink.load_library()
     if args.workload == "diff":
         bench_diff(args, np, torch, blink, synth, dev)
+    elif args.workload == "dynspec":
+        bench_dynspec(args, np, torch, blink, synth, dev)
     else:
         bench_images(args, np, torch, blink, synth, dev)
 

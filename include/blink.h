@@ -220,6 +220,36 @@ blink_status blink_image_batch_timed(const blink_problem* p, const blink_inputs*
                                      size_t ws_bytes, blink_stream_t stream,
                                      blink_kernel_times* times);
 
+/*
+ * blink_dynamic_spectra: per-pixel time series of an image cube, with a
+ * reference image subtracted (Sec. 2: dynamic spectra of every pixel are
+ * formed from the cube of images and searched for transients; dirty-image
+ * artefacts are removed by subtracting a reference image of the same field,
+ * which Sec. 4.3 takes as the preceding image, an average of the preceding
+ * images or a model image).
+ *   images  [n_time][n_chan][n_pix] float (n_pix = M*M, the images of
+ *           blink_image_batch as they come out), device, read only;
+ *   spectra [n_pix][n_chan][n_time] float, device, written; must not
+ *           overlap images;
+ *   ref_mode BLINK_REF_NONE:  spectra[p][c][t] = images[t][c][p];
+ *            BLINK_REF_MEAN:  images[t][c][p] minus the mean of the
+ *                             k = min(ref_len, t) preceding images at (c, p),
+ *                             evaluated in double and rounded once; 0 at t = 0
+ *                             (ref_len in 1..BLINK_REF_MAX_LEN; 1 = preceding
+ *                             image);
+ *            BLINK_REF_MODEL: images[t][c][p] - ref_image[c][p] (FP32);
+ *   ref_image [n_chan][n_pix] float, device; required for BLINK_REF_MODEL,
+ *           ignored otherwise.
+ * Errors: BLINK_E_SIZE for negative sizes, n_chan > 65535 or element counts
+ * beyond 2^62; BLINK_E_ARG for null required pointers, an unknown mode or
+ * ref_len out of range. No workspace; enqueued on `stream`.
+ */
+typedef enum { BLINK_REF_NONE = 0, BLINK_REF_MEAN = 1, BLINK_REF_MODEL = 2 } blink_reference;
+#define BLINK_REF_MAX_LEN 128
+blink_status blink_dynamic_spectra(const float* images, int32_t n_time, int32_t n_chan, int32_t n_pix,
+                                   int32_t ref_mode, int32_t ref_len, const float* ref_image,
+                                   float* spectra, blink_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,7 +24,11 @@ STATUS = {0: "BLINK_OK", -1: "BLINK_E_ARG", -2: "BLINK_E_SIZE", -3: "BLINK_E_UNS
 
 # every symbol include/blink.h declares
 EXPORTS = ("blink_status_string", "blink_supported_n", "blink_workspace_size", "blink_grid",
-           "blink_fft2d", "blink_image_batch", "blink_degrid_adjoint", "blink_image_batch_timed")
+           "blink_fft2d", "blink_image_batch", "blink_degrid_adjoint", "blink_image_batch_timed",
+           "blink_dynamic_spectra")
+
+REF_NONE, REF_MEAN, REF_MODEL = 0, 1, 2
+REF_MAX_LEN = 128
 
 # kernel classes reported by blink_image_batch_timed
 KCLASS = ("sort", "bounds", "grid_cols", "rows")
@@ -86,6 +90,8 @@ def load_library(path: str | None = None):
     lib.blink_degrid_adjoint.restype = i32
     lib.blink_image_batch_timed.argtypes = [P, I, vp, vp, vp, sz, vp, ctypes.POINTER(KernelTimes)]
     lib.blink_image_batch_timed.restype = i32
+    lib.blink_dynamic_spectra.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp, vp]
+    lib.blink_dynamic_spectra.restype = i32
     if path is None:
         _lib = lib
     return lib
@@ -279,6 +285,31 @@ def degrid_adjoint(image_grad, vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=N
                                     _stream(stream))
     _check(code, "blink_degrid_adjoint")
     return vg, gg
+
+
+def dynamic_spectra(images, ref_mode=REF_NONE, ref_len=1, ref_image=None, out=None, stream=None):
+    """Per-pixel time series [P][C][T] of an image cube [T][C][M][M] (blink_dynamic_spectra).
+
+    ``ref_mode`` REF_NONE transposes; REF_MEAN subtracts the mean of the
+    ``ref_len`` preceding images (0 at t = 0); REF_MODEL subtracts
+    ``ref_image`` [C][M][M].
+    """
+    lib = load_library()
+    _dev(images, "images", torch.float32)
+    if images.dim() != 4 or images.shape[2] != images.shape[3]:
+        raise ValueError("images must be [T][C][M][M]")
+    T, C, M = images.shape[0], images.shape[1], images.shape[2]
+    P = M * M
+    if ref_mode == REF_MODEL:
+        _dev(ref_image, "ref_image", torch.float32, (C, M, M))
+    if out is None:
+        out = torch.empty((P, C, T), dtype=torch.float32, device=images.device)
+    _dev(out, "out", torch.float32, (P, C, T))
+    code = lib.blink_dynamic_spectra(_ptr(images), T, C, P, int(ref_mode), int(ref_len),
+                                     _ptr(ref_image) if ref_mode == REF_MODEL else None, _ptr(out),
+                                     _stream(stream))
+    _check(code, "blink_dynamic_spectra")
+    return out
 
 
 class BlinkImage(torch.autograd.Function):

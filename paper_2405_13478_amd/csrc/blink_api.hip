@@ -179,12 +179,13 @@ struct Timer {
   bool on = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
   int cls = -1;
+  bool bad = false;                      // an event record failed: timings are not trustworthy
   hipEvent_t cur = nullptr;
   void begin(int c) {
     if (!on) return;
     hipEvent_t e = nullptr;
     if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
-    hipEventRecord(e, st);
+    if (hipEventRecord(e, st) != hipSuccess) bad = true;
     cls = c;
     cur = e;
   }
@@ -192,22 +193,23 @@ struct Timer {
     if (!on || !cur) return;
     hipEvent_t e = nullptr;
     if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
-    hipEventRecord(e, st);
+    if (hipEventRecord(e, st) != hipSuccess) bad = true;
     ev.push_back({cls, {cur, e}});
     cur = nullptr;
   }
   blink_status collect(blink_kernel_times* out) {
     for (int k = 0; k < BLINK_KCLASS_COUNT; ++k) { out->ms[k] = 0.0; out->launches[k] = 0; }
-    blink_status r = BLINK_OK;
-    if (!ev.empty() && hipEventSynchronize(ev.back().second.second) != hipSuccess) r = BLINK_E_HIP;
+    blink_status r = bad ? BLINK_E_HIP : BLINK_OK;
+    if (r == BLINK_OK && !ev.empty() && hipEventSynchronize(ev.back().second.second) != hipSuccess)
+      r = BLINK_E_HIP;
     for (auto& x : ev) {
       float ms = 0.f;
       if (r == BLINK_OK && hipEventElapsedTime(&ms, x.second.first, x.second.second) == hipSuccess) {
         out->ms[x.first] += ms;
         out->launches[x.first] += 1;
       }
-      hipEventDestroy(x.second.first);
-      hipEventDestroy(x.second.second);
+      (void)hipEventDestroy(x.second.first);
+      (void)hipEventDestroy(x.second.second);
     }
     ev.clear();
     return r;
@@ -612,6 +614,36 @@ blink_status blink_degrid_adjoint(const blink_problem* p, const blink_inputs* in
 #define BLINK_ADJ_CALL(n) adjoint_n<n>(p, a, chunk, st)
   BLINK_DISPATCH_N(p->grid_n, BLINK_ADJ_CALL)
 #undef BLINK_ADJ_CALL
+}
+
+blink_status blink_dynamic_spectra(const float* images, int32_t n_time, int32_t n_chan, int32_t n_pix,
+                                   int32_t ref_mode, int32_t ref_len, const float* ref_image,
+                                   float* spectra, blink_stream_t stream) {
+  if (n_time < 0 || n_chan < 0 || n_pix < 0 || n_chan > MAX_GRID_Y) return BLINK_E_SIZE;
+  if ((double)n_time * n_chan * n_pix > 4.0e18) return BLINK_E_SIZE;
+  if (ref_mode < BLINK_REF_NONE || ref_mode > BLINK_REF_MODEL) return BLINK_E_ARG;
+  static_assert(BLINK_REF_MAX_LEN <= DS_KMAX, "window beyond the kernel's halo");
+  if (ref_mode == BLINK_REF_MEAN && (ref_len < 1 || ref_len > BLINK_REF_MAX_LEN)) return BLINK_E_ARG;
+  const long long n = (long long)n_time * n_chan * n_pix;
+  if (n == 0) return BLINK_OK;
+  if (!images || !spectra) return BLINK_E_ARG;
+  if (ref_mode == BLINK_REF_MODEL && !ref_image) return BLINK_E_ARG;
+  const int k = ref_mode == BLINK_REF_MEAN ? ref_len : 0;
+  const long long npt8 = ((n_pix + DS_PP - 1) / DS_PP + 7) / 8 * 8;   // pixel tiles, padded to 8
+  const long long ntt = (n_time + DS_TT - 1) / DS_TT;
+  const long long wgs = npt8 * ntt * n_chan;
+  if (wgs > INT32_MAX) return BLINK_E_SIZE;
+  const dim3 g((unsigned)wgs);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const bool vec = n_pix % 4 == 0 && n_time % 4 == 0 && ((uintptr_t)images % 16) == 0 &&
+                   ((uintptr_t)spectra % 16) == 0;
+  if (vec)
+    hipLaunchKernelGGL((k_dynspec<true>), g, dim3(DS_THREADS), dynspec_lds(k), st, images, (int)n_time,
+                       (int)n_chan, (long long)n_pix, (int)ref_mode, k, ref_image, spectra, (int)npt8);
+  else
+    hipLaunchKernelGGL((k_dynspec<false>), g, dim3(DS_THREADS), dynspec_lds(k), st, images, (int)n_time,
+                       (int)n_chan, (long long)n_pix, (int)ref_mode, k, ref_image, spectra, (int)npt8);
+  return launched();
 }
 
 }  // extern "C"

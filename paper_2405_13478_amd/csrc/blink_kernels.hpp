@@ -831,6 +831,138 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
   }
 }
 
+// ============================================================== dynamic spectra
+// Transpose of the image cube [T][C][P] to per-pixel time series [P][C][T]
+// with the reference image subtracted on the way. One workgroup per tile of
+// DS_TT timesteps x DS_PP pixels of one channel: the rows of the tile (and,
+// for a mean over K preceding images, the K rows before it) are read with
+// consecutive pixels on consecutive lanes, all loads of a thread issued
+// before the first is used; the differences are formed per pixel and staged
+// in LDS as [pixel][time]; each pixel's series is then written with
+// consecutive timesteps on consecutive lanes. VEC moves 16 bytes per lane
+// (P and T multiples of 4, 16-byte aligned arrays).
+// Grid: one dimension, workgroup L on XCD L mod 8. The channel varies fastest
+// among the workgroups of an XCD, and all time tiles of a pixel tile share
+// its XCD, so the series of (p, c) and (p, c + 1), adjacent in the output,
+// are written close together into the same L2 and leave it as whole lines.
+constexpr int DS_TT = 128, DS_PP = 64, DS_THREADS = 256, DS_KMAX = 128;
+constexpr int DS_ST = DS_PP + 1;                              // LDS row stride (floats)
+
+// One LDS buffer of DS_TT + K rows: the differences overwrite the tile's own
+// rows once every thread has read its window, and the stores read them back
+// column-wise (the odd stride keeps both directions off a single bank).
+__host__ __device__ constexpr size_t dynspec_lds(int k) {
+  return (size_t)(DS_TT + k) * DS_ST * sizeof(float);
+}
+
+template <bool VEC>
+__global__ void __launch_bounds__(DS_THREADS) k_dynspec(const float* __restrict__ img, int T, int C, long long P,
+                                                        int mode, int K, const float* __restrict__ ref,
+                                                        float* __restrict__ out, int npt8) {
+  extern __shared__ float4 lds_raw[];
+  float* rows = reinterpret_cast<float*>(lds_raw);            // [DS_TT + K][DS_ST]
+  const long long L = blockIdx.x;
+  const long long r8 = L >> 3;
+  const int c = (int)(r8 % C);
+  const long long u = (r8 / C) * 8 + (L & 7);                // tile: u = time tile * npt8 + pixel tile
+  const long long pt = u % npt8;
+  const int tt = (int)(u / npt8);
+  const long long p0 = pt * DS_PP;
+  const int t0 = tt * DS_TT;
+  if (p0 >= P || t0 >= T) return;                             // padding of the pixel tiles to 8
+  const int r0 = t0 - K;                                      // first row held (may be < 0)
+  const int nrows = DS_TT + K;
+  if constexpr (VEC) {
+    constexpr int Q = DS_PP / 4;                              // float4 per row
+    constexpr int MAXI = (DS_TT + DS_KMAX) * Q / DS_THREADS;
+    float4 v[MAXI];
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) {
+      const int e = threadIdx.x + i * DS_THREADS;
+      const int r = e / Q, q = e % Q;
+      const int t = r0 + r;
+      const long long p = p0 + 4 * q;
+      v[i] = (r < nrows && t >= 0 && t < T && p < P)
+                 ? *reinterpret_cast<const float4*>(img + ((long long)t * C + c) * P + p)
+                 : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) {
+      const int e = threadIdx.x + i * DS_THREADS;
+      const int r = e / Q, q = e % Q;
+      if (r < nrows) {
+        float* d = rows + r * DS_ST + 4 * q;
+        d[0] = v[i].x; d[1] = v[i].y; d[2] = v[i].z; d[3] = v[i].w;
+      }
+    }
+  } else {
+    for (int e = threadIdx.x; e < nrows * DS_PP; e += DS_THREADS) {
+      const int r = e / DS_PP, jj = e % DS_PP;
+      const int t = r0 + r;
+      const long long p = p0 + jj;
+      rows[r * DS_ST + jj] = (t >= 0 && t < T && p < P) ? img[((long long)t * C + c) * P + p] : 0.0f;
+    }
+  }
+  __syncthreads();
+  // thread = (pixel j, segment g of the tile's timesteps)
+  const int j = threadIdx.x % DS_PP, g = threadIdx.x / DS_PP;
+  constexpr int SEG = DS_TT / (DS_THREADS / DS_PP);
+  const float rv = (mode == 2 && p0 + j < P) ? ref[(long long)c * P + p0 + j] : 0.0f;
+  double win = 0.0;                                           // sum of the k preceding images
+  const int ta = t0 + g * SEG;
+  if (mode == 1) {
+    const int k = min(K, ta);
+    for (int s = ta - k; s < ta; ++s) win += (double)rows[(s - r0) * DS_ST + j];
+  }
+  float dv[SEG];
+#pragma unroll
+  for (int i = 0; i < SEG; ++i) {
+    const int t = ta + i;
+    const float x = rows[(t - r0) * DS_ST + j];
+    float d;
+    if (mode == 0) {
+      d = x;
+    } else if (mode == 2) {
+      d = x - rv;
+    } else {
+      // mean of the window: 1/k is exact for k a power of two and within an
+      // ulp of double otherwise, far below the final rounding to float
+      const int k = min(K, t);
+      d = t == 0 ? 0.0f : (float)((double)x - win * (1.0 / (double)k));
+      // slide the window to end at t: add x, drop the image K behind
+      win += (double)x;
+      if (t - K >= 0) win -= (double)rows[(t - K - r0) * DS_ST + j];
+    }
+    dv[i] = d;
+  }
+  __syncthreads();                                            // every window has been read
+#pragma unroll
+  for (int i = 0; i < SEG; ++i) rows[(ta + i - r0) * DS_ST + j] = dv[i];
+  __syncthreads();
+  if constexpr (VEC) {
+    constexpr int Q = DS_TT / 4;                              // float4 per pixel series
+#pragma unroll
+    for (int i = 0; i < DS_PP * Q / DS_THREADS; ++i) {
+      const int e = threadIdx.x + i * DS_THREADS;
+      const int pj = e / Q, q = e % Q;
+      const long long p = p0 + pj;
+      const int t = t0 + 4 * q;
+      if (p < P && t < T) {
+        const float* src = rows + (t - r0) * DS_ST + pj;
+        *reinterpret_cast<float4*>(out + (p * C + c) * T + t) =
+            make_float4(src[0], src[DS_ST], src[2 * DS_ST], src[3 * DS_ST]);
+      }
+    }
+  } else {
+    for (int e = threadIdx.x; e < DS_PP * DS_TT; e += DS_THREADS) {
+      const int pj = e / DS_TT, tq = e % DS_TT;
+      const long long p = p0 + pj;
+      const int t = t0 + tq;
+      if (p < P && t < T) out[(p * C + c) * T + t] = rows[(t - r0) * DS_ST + pj];
+    }
+  }
+}
+
 // ============================================================== plain 2D FFT
 template <int N>
 struct Fft2 {

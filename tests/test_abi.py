@@ -169,3 +169,16 @@ def test_kernel_gridding_has_no_adjoint(lib):
     # the same problem without the kernel passes validation (and then needs a workspace)
     p0 = _prob()
     assert a(ctypes.byref(p0), ctypes.byref(_inputs()), FAKE, FAKE, None, None, 0, None) == E_WS
+
+
+def test_dynamic_spectra_validation(lib):
+    d = lib.blink_dynamic_spectra
+    assert d(FAKE, -1, 2, 16, 0, 1, None, FAKE, None) == E_SIZE
+    assert d(FAKE, 4, 70000, 16, 0, 1, None, FAKE, None) == E_SIZE        # channels on grid.z
+    assert d(FAKE, 4, 2, 16, 3, 1, None, FAKE, None) == E_ARG              # unknown mode
+    assert d(FAKE, 4, 2, 16, 1, 0, None, FAKE, None) == E_ARG              # window 0
+    assert d(FAKE, 4, 2, 16, 1, B.REF_MAX_LEN + 1, None, FAKE, None) == E_ARG
+    assert d(FAKE, 4, 2, 16, 2, 1, None, FAKE, None) == E_ARG              # model without image
+    assert d(None, 4, 2, 16, 0, 1, None, FAKE, None) == E_ARG
+    assert d(FAKE, 4, 2, 16, 0, 1, None, None, None) == E_ARG
+    assert d(None, 0, 2, 16, 0, 1, None, None, None) == E_OK               # empty: nothing to do
