@@ -11,3 +11,4 @@ from .blink_oracle import (C_LIGHT, NATURAL, UNIFORM, NORM_NONE, NORM_WEIGHTS,  
                            adjoint_one, adjoint_batch, fft_flops_estimate)
 from . import kernel_gridding  # noqa: F401,E402
 from . import dynamic_spectra  # noqa: F401,E402
+from . import correlator  # noqa: F401,E402
