@@ -245,6 +245,28 @@ blink_status blink_image_batch_timed(const blink_problem* p, const blink_inputs*
  * ref_len out of range. No workspace; enqueued on `stream`.
  */
 typedef enum { BLINK_REF_NONE = 0, BLINK_REF_MEAN = 1, BLINK_REF_MODEL = 2 } blink_reference;
+
+/*
+ * blink_correlate: the X-engine of an FX correlator (Sec. 4.1): for every
+ * integration t and channel c, the products of the channelised complex
+ * voltages of all antenna pairs, accumulated over the integration's samples:
+ *   V_ij = sum_s x_i(s) conj(x_j(s))   (the conjugate on the second antenna;
+ *                                        the equation as printed omits it)
+ *   volt  [n_time][n_chan][n_ant][n_samp][2] int8 (real, imaginary), device,
+ *         16-byte aligned;
+ *   vis   [n_time][n_chan][n_ant (n_ant - 1) / 2] blink_c32, device: pairs
+ *         i < j in row-major upper-triangle order (the baseline order that
+ *         blink_image_batch's inputs use with ant1 = i, ant2 = j);
+ *   autos [n_time][n_chan][n_ant] float V_aa, device, or NULL.
+ * Integer products on the matrix cores, summed exactly in int32, then
+ * converted to float (exact below 2^24 in magnitude). The plain sum, not
+ * the average, is returned.
+ * Errors: BLINK_E_SIZE for negative sizes, n_ant < 2 with T*C > 0, n_samp not
+ * a multiple of 16 or above 65536, or counts beyond 2^62; BLINK_E_ARG for null
+ * or misaligned required pointers. No workspace; enqueued on `stream`.
+ */
+blink_status blink_correlate(const int8_t* volt, int32_t n_time, int32_t n_chan, int32_t n_ant,
+                             int32_t n_samp, blink_c32* vis, float* autos, blink_stream_t stream);
 #define BLINK_REF_MAX_LEN 128
 blink_status blink_dynamic_spectra(const float* images, int32_t n_time, int32_t n_chan, int32_t n_pix,
                                    int32_t ref_mode, int32_t ref_len, const float* ref_image,

@@ -25,7 +25,7 @@ STATUS = {0: "BLINK_OK", -1: "BLINK_E_ARG", -2: "BLINK_E_SIZE", -3: "BLINK_E_UNS
 # every symbol include/blink.h declares
 EXPORTS = ("blink_status_string", "blink_supported_n", "blink_workspace_size", "blink_grid",
            "blink_fft2d", "blink_image_batch", "blink_degrid_adjoint", "blink_image_batch_timed",
-           "blink_dynamic_spectra")
+           "blink_dynamic_spectra", "blink_correlate")
 
 REF_NONE, REF_MEAN, REF_MODEL = 0, 1, 2
 REF_MAX_LEN = 128
@@ -92,6 +92,8 @@ def load_library(path: str | None = None):
     lib.blink_image_batch_timed.restype = i32
     lib.blink_dynamic_spectra.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp, vp]
     lib.blink_dynamic_spectra.restype = i32
+    lib.blink_correlate.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp]
+    lib.blink_correlate.restype = i32
     if path is None:
         _lib = lib
     return lib
@@ -310,6 +312,23 @@ def dynamic_spectra(images, ref_mode=REF_NONE, ref_len=1, ref_image=None, out=No
                                      _stream(stream))
     _check(code, "blink_dynamic_spectra")
     return out
+
+
+def correlate(volt, vis=None, autos=False, stream=None):
+    """X-engine (blink_correlate): int8 voltages [T][C][A][S][2] -> (vis [T][C][B] c64, autos or None)."""
+    lib = load_library()
+    _dev(volt, "volt", torch.int8)
+    if volt.dim() != 5 or volt.shape[4] != 2:
+        raise ValueError("volt must be [T][C][A][S][2] int8")
+    T, C, A, S = (int(d) for d in volt.shape[:4])
+    B = A * (A - 1) // 2
+    if vis is None:
+        vis = torch.empty((T, C, B), dtype=torch.complex64, device=volt.device)
+    _dev(vis, "vis", torch.complex64, (T, C, B))
+    au = torch.empty((T, C, A), dtype=torch.float32, device=volt.device) if autos else None
+    code = lib.blink_correlate(_ptr(volt), T, C, A, S, _ptr(vis), _ptr(au), _stream(stream))
+    _check(code, "blink_correlate")
+    return vis, au
 
 
 class BlinkImage(torch.autograd.Function):

@@ -646,4 +646,28 @@ blink_status blink_dynamic_spectra(const float* images, int32_t n_time, int32_t 
   return launched();
 }
 
+blink_status blink_correlate(const int8_t* volt, int32_t n_time, int32_t n_chan, int32_t n_ant,
+                             int32_t n_samp, blink_c32* vis, float* autos, blink_stream_t stream) {
+  if (n_time < 0 || n_chan < 0 || n_ant < 0 || n_samp < 0) return BLINK_E_SIZE;
+  const long long nimg = (long long)n_time * n_chan;
+  if (nimg == 0) return BLINK_OK;
+  if (n_ant < 2 || n_samp % 16 != 0 || n_samp > 65536) return BLINK_E_SIZE;
+  if ((double)nimg * n_ant * n_samp * 2 > 4.0e18) return BLINK_E_SIZE;
+  if (!vis || (n_samp > 0 && !volt)) return BLINK_E_ARG;
+  if ((uintptr_t)volt % 16 != 0) return BLINK_E_ARG;
+  XeArgs a{};
+  a.volt = volt;
+  a.vis = reinterpret_cast<float2*>(vis);
+  a.autos = autos;
+  a.T = n_time; a.C = n_chan; a.A = n_ant; a.S = n_samp;
+  a.nb = (n_ant + XE_BLK - 1) / XE_BLK;
+  a.npairs = a.nb * (a.nb + 1) / 2;
+  a.nimg = nimg;
+  const long long wgs = (nimg + 7) / 8 * 8 * a.npairs;
+  if (wgs > INT32_MAX) return BLINK_E_SIZE;
+  // (n_samp = 0 runs no step and writes zeros)
+  hipLaunchKernelGGL(k_xengine, dim3((unsigned)wgs), dim3(WAVE), 0, reinterpret_cast<hipStream_t>(stream), a);
+  return launched();
+}
+
 }  // extern "C"

@@ -963,6 +963,98 @@ __global__ void __launch_bounds__(DS_THREADS) k_dynspec(const float* __restrict_
   }
 }
 
+// ============================================================== correlator X-engine
+// V_ij = sum_s x_i(s) conj(x_j(s)) for 8-bit complex voltages x[t][c][a][s]
+// (real, imaginary interleaved), on the matrix cores. With x = r + i q:
+//   Re V_ij = sum r_i r_j + q_i q_j,   Im V_ij = sum q_i r_j - r_i q_j,
+// i.e. integer matrix products of the antenna-by-sample matrices R and Q.
+// One wavefront computes a 32 x 32 block of antenna pairs (block row bi <=
+// block column bj) with v_mfma_i32_32x32x32_i8, 32 samples per step: each
+// lane loads 16 complex samples (32 bytes) of one antenna for the A operand
+// (row antenna) and of one for the B operand (column antenna), splits the
+// real and imaginary bytes with byte permutes, and issues four products
+// into three int32 accumulators (RR + QQ, QR, RQ). Sums are exact in int32
+// for up to 65536 samples. The workgroups of one (t, c) run on one XCD so
+// that its voltages are read from HBM once and served to every block pair
+// from that XCD's L2.
+typedef int xe_v4i __attribute__((ext_vector_type(4)));
+typedef int xe_v16i __attribute__((ext_vector_type(16)));
+
+constexpr int XE_BLK = 32;      // antennas per block (the MFMA tile edge)
+constexpr int XE_STEP = 32;     // samples per MFMA step (16 per half-wavefront)
+
+struct XeArgs {
+  const int8_t* volt;           // [T][C][A][S][2]
+  float2* vis;                  // [T][C][A(A-1)/2]
+  float* autos;                 // [T][C][A] or null
+  int T, C, A, S;
+  int nb;                       // antenna blocks: ceil(A / 32)
+  int npairs;                   // nb (nb + 1) / 2 block pairs per (t, c)
+  long long nimg;               // T * C
+};
+
+// Real and imaginary bytes of 16 interleaved complex int8 samples (32 bytes).
+__device__ __forceinline__ void xe_split(const uint4 lo, const uint4 hi, xe_v4i& re, xe_v4i& im) {
+  // v_perm_b32 picks bytes of the 64-bit value {a, b} (b = bytes 0-3)
+  re.x = __builtin_amdgcn_perm(lo.y, lo.x, 0x06040200u);
+  im.x = __builtin_amdgcn_perm(lo.y, lo.x, 0x07050301u);
+  re.y = __builtin_amdgcn_perm(lo.w, lo.z, 0x06040200u);
+  im.y = __builtin_amdgcn_perm(lo.w, lo.z, 0x07050301u);
+  re.z = __builtin_amdgcn_perm(hi.y, hi.x, 0x06040200u);
+  im.z = __builtin_amdgcn_perm(hi.y, hi.x, 0x07050301u);
+  re.w = __builtin_amdgcn_perm(hi.w, hi.z, 0x06040200u);
+  im.w = __builtin_amdgcn_perm(hi.w, hi.z, 0x07050301u);
+}
+
+__global__ void __launch_bounds__(WAVE) k_xengine(XeArgs a) {
+  const long long L = blockIdx.x;
+  const long long r8 = L >> 3;
+  const long long img = (r8 / a.npairs) * 8 + (L & 7);
+  if (img >= a.nimg) return;                                  // padding of the last group of 8
+  int pr = (int)(r8 % a.npairs);
+  int bi = 0;                                                 // block pair -> (bi <= bj)
+  while (pr >= a.nb - bi) { pr -= a.nb - bi; ++bi; }
+  const int bj = bi + pr;
+  const int lane = threadIdx.x;
+  const int h = lane >> 5, q = lane & 31;
+  const int ai = bi * XE_BLK + q, aj = bj * XE_BLK + q;       // operand antennas of this lane
+  const size_t rowb = (size_t)a.S * 2;                        // bytes per antenna row
+  const int8_t* base = a.volt + (size_t)img * a.A * rowb;
+  const bool oki = ai < a.A, okj = aj < a.A;
+  const uint4* pi = reinterpret_cast<const uint4*>(base + (size_t)(oki ? ai : 0) * rowb);
+  const uint4* pj = reinterpret_cast<const uint4*>(base + (size_t)(okj ? aj : 0) * rowb);
+  xe_v16i rr = {0}, qr = {0}, rq = {0};
+  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+  for (int s0 = 0; s0 < a.S; s0 += XE_STEP) {
+    const int s = s0 + 16 * h;                                // this half-wavefront's 16 samples
+    const bool in = s < a.S;                                  // S is a multiple of 16
+    const int u = s >> 3;                                     // uint4 index: 8 samples per 16 bytes
+    const uint4 i0 = (oki && in) ? pi[u] : z, i1 = (oki && in) ? pi[u + 1] : z;
+    const uint4 j0 = (okj && in) ? pj[u] : z, j1 = (okj && in) ? pj[u + 1] : z;
+    xe_v4i ar, aq, br, bq;
+    xe_split(i0, i1, ar, aq);
+    xe_split(j0, j1, br, bq);
+    rr = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar, br, rr, 0, 0, 0);
+    rr = __builtin_amdgcn_mfma_i32_32x32x32_i8(aq, bq, rr, 0, 0, 0);
+    qr = __builtin_amdgcn_mfma_i32_32x32x32_i8(aq, br, qr, 0, 0, 0);
+    rq = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar, bq, rq, 0, 0, 0);
+  }
+  // accumulator r of lane (h, q) holds row i = bi*32 + (r % 4) + 8 (r / 4) + 4 h, column j = bj*32 + q
+  const size_t nbl = (size_t)a.A * (a.A - 1) / 2;
+  float2* v = a.vis + (size_t)img * nbl;
+  const int j = bj * XE_BLK + q;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = bi * XE_BLK + (r & 3) + 8 * (r >> 2) + 4 * h;
+    if (j < a.A && i < j) {
+      const size_t b = (size_t)i * a.A - (size_t)i * (i + 1) / 2 + (j - i - 1);
+      v[b] = make_float2((float)rr[r], (float)(qr[r] - rq[r]));
+    } else if (a.autos != nullptr && i == j && j < a.A) {
+      a.autos[(size_t)img * a.A + i] = (float)rr[r];
+    }
+  }
+}
+
 // ============================================================== plain 2D FFT
 template <int N>
 struct Fft2 {
