@@ -530,6 +530,57 @@ def bench_dynspec(args, np, torch, blink, synth, dev):
     print(json.dumps(out_line), flush=True)
 
 
+INT8_PEAK_TOPS = 5000.0         # MI355X dense int8 matrix peak, TOP/s
+
+
+def bench_xengine(args, np, torch, blink, dev):
+    """Correlator X-engine: 256 antennas, 32 channels, 64 integrations of 4096 int8 samples."""
+    T, C, A, S = 64, 32, 256, 4096
+    g = torch.Generator(device=dev)
+    g.manual_seed(20240521 + 6)
+    volt = torch.randint(-128, 128, (T, C, A, S, 2), dtype=torch.int8, device=dev, generator=g)
+    B = A * (A - 1) // 2
+    vis = torch.empty((T, C, B), dtype=torch.complex64, device=dev)
+    for _ in range(args.warmup):
+        blink.correlate(volt, vis=vis)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(args.steps):
+        blink.correlate(volt, vis=vis)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    n = T * C
+    ops = 8.0 * (A * (A + 1) / 2) * S * n          # 4 real multiply-adds per complex product, pairs incl. autos
+    hbm = n * (A * S * 2 + B * 8)
+    out = {
+        "metric": "integrations x channels correlated/s (xengine)", "value": round(n / (ms / 1e3), 1),
+        "unit": "spectra/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i8 (i32 accumulation)",
+        "data": "synthetic",
+        "config": {"workload": f"X-engine: {A} antennas ({B} baselines), {C} channels x {T} integrations of "
+                               f"{S} complex int8 samples", "antennas": A, "samples": S, "spectra_per_step": n},
+        "roofline": {"bound": "mfma", "achieved": round(ops / (ms * 1e-3) / 1e12, 1), "peak": INT8_PEAK_TOPS,
+                     "unit": "TOP/s", "frac": round(ops / (ms * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4), "traffic": None,
+                     "kernel": "xengine", "mean_launch_ms": round(ms, 5), "algorithmic_ops_per_launch": ops,
+                     "hbm_gbs_algorithmic": round(hbm / (ms * 1e-3) / 1e9, 1)},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        from threadpoolctl import threadpool_info
+        sub = volt[:1, :16].cpu().numpy()
+        t0 = time.perf_counter()
+        oracle.correlator.correlate(sub)
+        dt = time.perf_counter() - t0
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        out["cpu_baseline"] = {"value": round(16 / dt, 3), "unit": "spectra/s", "cores": threads, "kind": "oracle",
+                               "sample": f"1 integration x 16 channels of the same data (numpy complex matmul), "
+                                         f"{dt:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
 # ---------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -537,7 +588,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="widefield",
-                    choices=("widefield", "widefield_kb", "plain", "allsky", "diff", "precision", "dynspec"))
+                    choices=("widefield", "widefield_kb", "plain", "allsky", "diff", "precision", "dynspec",
+                             "xengine"))
     ap.add_argument("--timesteps-per-step", type=int, default=None)
     ap.add_argument("--timesteps", type=int, default=None,
                     help="timesteps of the job generated into HBM (default: the whole widefield job)")
@@ -561,7 +613,7 @@ def main():
               "images shard across GPUs with no exchange, see DESIGN.md", file=sys.stderr)
         sys.exit(2)
     defaults = {"widefield": (20, 3), "widefield_kb": (10, 2), "plain": (500, 20), "allsky": (3, 1),
-                "diff": (5, 2), "precision": (5, 1), "dynspec": (10, 2)}
+                "diff": (5, 2), "precision": (5, 1), "dynspec": (10, 2), "xengine": (10, 2)}
     ds, dw = defaults[args.workload]
     args.steps = ds if args.steps is None else args.steps
     args.warmup = dw if args.warmup is None else args.warmup
@@ -586,6 +638,8 @@ def main():
         bench_diff(args, np, torch, blink, synth, dev)
     elif args.workload == "dynspec":
         bench_dynspec(args, np, torch, blink, synth, dev)
+    elif args.workload == "xengine":
+        bench_xengine(args, np, torch, blink, dev)
     else:
         bench_images(args, np, torch, blink, synth, dev)
 

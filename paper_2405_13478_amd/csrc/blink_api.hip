@@ -660,8 +660,8 @@ blink_status blink_correlate(const int8_t* volt, int32_t n_time, int32_t n_chan,
   a.vis = reinterpret_cast<float2*>(vis);
   a.autos = autos;
   a.T = n_time; a.C = n_chan; a.A = n_ant; a.S = n_samp;
-  a.nb = (n_ant + XE_BLK - 1) / XE_BLK;
-  a.npairs = a.nb * (a.nb + 1) / 2;
+  a.nt = (n_ant + XE_TILE - 1) / XE_TILE;
+  a.npairs = a.nt * (a.nt + 1) / 2;
   a.nimg = nimg;
   const long long wgs = (nimg + 7) / 8 * 8 * a.npairs;
   if (wgs > INT32_MAX) return BLINK_E_SIZE;

@@ -968,19 +968,20 @@ __global__ void __launch_bounds__(DS_THREADS) k_dynspec(const float* __restrict_
 // (real, imaginary interleaved), on the matrix cores. With x = r + i q:
 //   Re V_ij = sum r_i r_j + q_i q_j,   Im V_ij = sum q_i r_j - r_i q_j,
 // i.e. integer matrix products of the antenna-by-sample matrices R and Q.
-// One wavefront computes a 32 x 32 block of antenna pairs (block row bi <=
-// block column bj) with v_mfma_i32_32x32x32_i8, 32 samples per step: each
-// lane loads 16 complex samples (32 bytes) of one antenna for the A operand
-// (row antenna) and of one for the B operand (column antenna), splits the
-// real and imaginary bytes with byte permutes, and issues four products
-// into three int32 accumulators (RR + QQ, QR, RQ). Sums are exact in int32
-// for up to 65536 samples. The workgroups of one (t, c) run on one XCD so
-// that its voltages are read from HBM once and served to every block pair
-// from that XCD's L2.
+// One wavefront computes a 64 x 64 tile of antenna pairs (tile row I <= tile
+// column J) as 2 x 2 blocks of 32 x 32 with v_mfma_i32_32x32x32_i8, 32
+// samples per step: each lane loads 16 complex samples (32 bytes) of each of
+// its two row antennas and two column antennas, splits real and imaginary
+// bytes with byte permutes, and issues 16 products into twelve int32
+// accumulator sets (RR + QQ, QR, RQ per block); every loaded operand feeds
+// two blocks. Loads run two steps ahead of the products. Sums are exact in
+// int32 for up to 65536 samples. The workgroups of one (t, c) run on one XCD,
+// so its voltages are read from HBM once and served to every tile from L2.
 typedef int xe_v4i __attribute__((ext_vector_type(4)));
 typedef int xe_v16i __attribute__((ext_vector_type(16)));
 
-constexpr int XE_BLK = 32;      // antennas per block (the MFMA tile edge)
+constexpr int XE_BLK = 32;      // antennas per MFMA block
+constexpr int XE_TILE = 64;     // antennas per wavefront tile edge (2 blocks)
 constexpr int XE_STEP = 32;     // samples per MFMA step (16 per half-wavefront)
 
 struct XeArgs {
@@ -988,8 +989,8 @@ struct XeArgs {
   float2* vis;                  // [T][C][A(A-1)/2]
   float* autos;                 // [T][C][A] or null
   int T, C, A, S;
-  int nb;                       // antenna blocks: ceil(A / 32)
-  int npairs;                   // nb (nb + 1) / 2 block pairs per (t, c)
+  int nt;                       // antenna tiles: ceil(A / 64)
+  int npairs;                   // nt (nt + 1) / 2 tile pairs per (t, c)
   long long nimg;               // T * C
 };
 
@@ -1012,47 +1013,84 @@ __global__ void __launch_bounds__(WAVE) k_xengine(XeArgs a) {
   const long long img = (r8 / a.npairs) * 8 + (L & 7);
   if (img >= a.nimg) return;                                  // padding of the last group of 8
   int pr = (int)(r8 % a.npairs);
-  int bi = 0;                                                 // block pair -> (bi <= bj)
-  while (pr >= a.nb - bi) { pr -= a.nb - bi; ++bi; }
-  const int bj = bi + pr;
+  int ti = 0;                                                 // tile pair -> (ti <= tj)
+  while (pr >= a.nt - ti) { pr -= a.nt - ti; ++ti; }
+  const int tj = ti + pr;
   const int lane = threadIdx.x;
   const int h = lane >> 5, q = lane & 31;
-  const int ai = bi * XE_BLK + q, aj = bj * XE_BLK + q;       // operand antennas of this lane
   const size_t rowb = (size_t)a.S * 2;                        // bytes per antenna row
   const int8_t* base = a.volt + (size_t)img * a.A * rowb;
-  const bool oki = ai < a.A, okj = aj < a.A;
-  const uint4* pi = reinterpret_cast<const uint4*>(base + (size_t)(oki ? ai : 0) * rowb);
-  const uint4* pj = reinterpret_cast<const uint4*>(base + (size_t)(okj ? aj : 0) * rowb);
-  xe_v16i rr = {0}, qr = {0}, rq = {0};
+  // operand antennas of this lane: rows ti*64 + {0, 32} + q, columns tj*64 + {0, 32} + q
+  const uint4* pa[4];
+  bool ok[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int ant = (k < 2 ? ti : tj) * XE_TILE + (k & 1) * XE_BLK + q;
+    ok[k] = ant < a.A;
+    pa[k] = reinterpret_cast<const uint4*>(base + (size_t)(ok[k] ? ant : 0) * rowb);
+  }
+  xe_v16i acc[2][2][3];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc[x][y][k] = xe_v16i{0};
   const uint4 z = make_uint4(0u, 0u, 0u, 0u);
-  for (int s0 = 0; s0 < a.S; s0 += XE_STEP) {
+  // operand bytes of step s0 (zeros beyond S or beyond A). Unconditional
+  // 16-byte loads from a clamped, valid address (antenna 0, first chunk),
+  // zeroed afterwards, so no branches sit in the load path.
+  auto fetch = [&](int s0, uint4 (&f)[8]) {
     const int s = s0 + 16 * h;                                // this half-wavefront's 16 samples
     const bool in = s < a.S;                                  // S is a multiple of 16
-    const int u = s >> 3;                                     // uint4 index: 8 samples per 16 bytes
-    const uint4 i0 = (oki && in) ? pi[u] : z, i1 = (oki && in) ? pi[u + 1] : z;
-    const uint4 j0 = (okj && in) ? pj[u] : z, j1 = (okj && in) ? pj[u + 1] : z;
-    xe_v4i ar, aq, br, bq;
-    xe_split(i0, i1, ar, aq);
-    xe_split(j0, j1, br, bq);
-    rr = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar, br, rr, 0, 0, 0);
-    rr = __builtin_amdgcn_mfma_i32_32x32x32_i8(aq, bq, rr, 0, 0, 0);
-    qr = __builtin_amdgcn_mfma_i32_32x32x32_i8(aq, br, qr, 0, 0, 0);
-    rq = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar, bq, rq, 0, 0, 0);
+    const int u = in ? s >> 3 : 0;                            // uint4 index: 8 samples per 16 bytes
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      f[2 * k] = pa[k][u];
+      f[2 * k + 1] = pa[k][u + 1];
+      if (!(ok[k] && in)) { f[2 * k] = z; f[2 * k + 1] = z; }
+    }
+  };
+  uint4 f0[8], f1[8];
+  if (a.S > 0) fetch(0, f0);                                  // (no samples: nothing to read)
+  for (int s0 = 0; s0 < a.S; s0 += XE_STEP) {
+    fetch(s0 + XE_STEP, f1);
+    xe_v4i r[4], qv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xe_split(f0[2 * k], f0[2 * k + 1], r[k], qv[k]);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        xe_v16i* c = acc[x][y];
+        c[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(r[x], r[2 + y], c[0], 0, 0, 0);
+        c[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(qv[x], r[2 + y], c[1], 0, 0, 0);
+        c[2] = __builtin_amdgcn_mfma_i32_32x32x32_i8(r[x], qv[2 + y], c[2], 0, 0, 0);
+        c[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(qv[x], qv[2 + y], c[0], 0, 0, 0);
+      }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) f0[k] = f1[k];
   }
-  // accumulator r of lane (h, q) holds row i = bi*32 + (r % 4) + 8 (r / 4) + 4 h, column j = bj*32 + q
+  // accumulator r of lane (h, q) in block (x, y) holds row
+  // i = ti*64 + 32x + (r % 4) + 8 (r / 4) + 4 h and column j = tj*64 + 32y + q
   const size_t nbl = (size_t)a.A * (a.A - 1) / 2;
   float2* v = a.vis + (size_t)img * nbl;
-  const int j = bj * XE_BLK + q;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = bi * XE_BLK + (r & 3) + 8 * (r >> 2) + 4 * h;
-    if (j < a.A && i < j) {
-      const size_t b = (size_t)i * a.A - (size_t)i * (i + 1) / 2 + (j - i - 1);
-      v[b] = make_float2((float)rr[r], (float)(qr[r] - rq[r]));
-    } else if (a.autos != nullptr && i == j && j < a.A) {
-      a.autos[(size_t)img * a.A + i] = (float)rr[r];
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const int j = tj * XE_TILE + y * XE_BLK + q;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = ti * XE_TILE + x * XE_BLK + (r & 3) + 8 * (r >> 2) + 4 * h;
+        if (j < a.A && i < j) {
+          const size_t b = (size_t)i * a.A - (size_t)i * (i + 1) / 2 + (j - i - 1);
+          v[b] = make_float2((float)acc[x][y][0][r], (float)(acc[x][y][1][r] - acc[x][y][2][r]));
+        } else if (a.autos != nullptr && i == j && j < a.A) {
+          a.autos[(size_t)img * a.A + i] = (float)acc[x][y][0][r];
+        }
+      }
     }
-  }
 }
 
 // ============================================================== plain 2D FFT
