@@ -17,6 +17,7 @@ kernel (per-launch HIP-event durations from the same timed steps) and the
 FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
+import glob
 import hashlib
 import json
 import math
@@ -103,16 +104,35 @@ def cpu_baseline(w, vis_cpu, sample, cores, ksup=0):
 # ---------------------------------------------------------------- rocprof summaries
 PROFILE_CMDS = {
     "stats": "rocprofv3 --kernel-trace --stats --output-format csv -d OUT/stats -o bench -- "
-             "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline",
+             "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --plain-loop 0",
     "fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'blink|copyBuffer' --output-format csv "
-             "-d OUT/pmc_FETCH_SIZE -o bench -- python3 bench.py --timesteps 10 --steps 1 --warmup 0 --no-cpu-baseline",
+             "-d OUT/pmc_FETCH_SIZE -o bench -- python3 bench.py --timesteps 10 --steps 1 --warmup 0 "
+             "--no-cpu-baseline --plain-loop 0",
     "write": "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'blink|copyBuffer' --output-format csv "
-             "-d OUT/pmc_WRITE_SIZE -o bench -- python3 bench.py --timesteps 10 --steps 1 --warmup 0 --no-cpu-baseline",
+             "-d OUT/pmc_WRITE_SIZE -o bench -- python3 bench.py --timesteps 10 --steps 1 --warmup 0 "
+             "--no-cpu-baseline --plain-loop 0",
     "copy_fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'blink|copyBuffer' --output-format csv "
                   "-d OUT/pmc_copy_FETCH_SIZE -o copy -- python3 bench.py --copy-calibration",
     "copy_write": "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'blink|copyBuffer' --output-format csv "
                   "-d OUT/pmc_copy_WRITE_SIZE -o copy -- python3 bench.py --copy-calibration",
 }
+# kernel statistics of the other workloads: (output folder, bench flags, summary file, title)
+EXTRA_STATS = {
+    "widefield_kb": ("stats_widefield_kb", "--workload widefield_kb --steps 3 --warmup 1 --no-cpu-baseline",
+                     "k_grid_cols_kb_k_rows_widefield1024_kernel_gridding_kernel_stats.md",
+                     "widefield 1024^2 -> 512^2 with a 6-cell Kaiser-Bessel gridding kernel, 7,680-image steps"),
+    "dynspec": ("stats_dynspec", "--workload dynspec --steps 5 --warmup 1 --no-cpu-baseline",
+                "k_dynspec_100x96_512sq_mean8_kernel_stats.md",
+                "dynamic spectra of 100 timesteps x 96 channels of 512^2 images, mean of 8 preceding images"),
+    "xengine": ("stats_xengine", "--workload xengine --steps 5 --warmup 1 --no-cpu-baseline",
+                "k_xengine_256ant_4096samp_kernel_stats.md",
+                "X-engine, 256 antennas, 32 channels x 64 integrations of 4096 int8 samples"),
+}
+
+
+def extra_stats_cmd(k):
+    d, flags, _, _ = EXTRA_STATS[k]
+    return f"rocprofv3 --kernel-trace --stats --output-format csv -d OUT/{d} -o bench -- python3 bench.py {flags}"
 KERNEL_KEYS = {"grid_cols": "k_grid_cols<1024, 0", "rows": "k_rows<1024"}
 
 
@@ -154,6 +174,23 @@ def summarize(out_dir):
                      f"{100 * float(r['TotalDurationNs']) / tot:.1f}% |")
     with open(os.path.join(prof, "k_grid_cols_k_rows_widefield1024_kernel_stats.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
+    for k, (d, _, fname, title) in EXTRA_STATS.items():
+        if not glob.glob(os.path.join(out_dir, d, "*_kernel_stats.csv")):
+            continue
+        st = _csv(os.path.join(out_dir, d, "*_kernel_stats.csv"))
+        tt = sum(float(r["TotalDurationNs"]) for r in st if "blink" in r["Name"]) or 1.0
+        ln = [f"# rocprofv3 kernel statistics: {title}", "",
+              "Command (from the repository root, with OUT the output folder):", "",
+              "    " + extra_stats_cmd(k), "", f"Library sources digest: `{digest}`", "",
+              "| kernel | calls | avg us | min us | max us | share of blink time |", "|---|---|---|---|---|---|"]
+        for r in sorted(st, key=lambda r: -float(r["TotalDurationNs"])):
+            if "blink" not in r["Name"]:
+                continue
+            ln.append(f"| `{r['Name'].replace('|', '/')}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                      f"{100 * float(r['TotalDurationNs']) / tt:.1f}% |")
+        with open(os.path.join(prof, fname), "w") as f:
+            f.write("\n".join(ln) + "\n")
 
     fe = _csv(os.path.join(out_dir, "pmc_FETCH_SIZE", "*_counter_collection.csv"))
     wr = _csv(os.path.join(out_dir, "pmc_WRITE_SIZE", "*_counter_collection.csv"))

@@ -313,9 +313,12 @@ constexpr size_t LDS_PER_CU = size_t(160) << 10;
 
 // Row pass: the block-store variant when the cutout half-width is a
 // multiple of the wavefront width (and the plan's last stage allows it).
+// Measured on MI355X: faster at N = 1024, slower than per-lane stores at
+// N = 2048 (4.85 against 4.1 ms per 384 images), so larger N keep those.
+constexpr int ROWS_BLOCK_STORE_MAX_N = 1024;
 template <int N, bool KB>
 void launch_rows(const blink_problem* p, ImgArgs& a, long long nwg, size_t lds, hipStream_t st) {
-  if constexpr (blocks_aligned(N)) {
+  if constexpr (blocks_aligned(N) && N <= ROWS_BLOCK_STORE_MAX_N) {
     if ((p->out_n / 2) % WAVE == 0) {
       hipLaunchKernelGGL((k_rows<N, true, KB>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), lds, st, a);
       return;
