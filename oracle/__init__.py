@@ -12,3 +12,4 @@ from .blink_oracle import (C_LIGHT, NATURAL, UNIFORM, NORM_NONE, NORM_WEIGHTS,  
 from . import kernel_gridding  # noqa: F401,E402
 from . import dynamic_spectra  # noqa: F401,E402
 from . import correlator  # noqa: F401,E402
+from . import phase_rotation  # noqa: F401,E402

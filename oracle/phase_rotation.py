@@ -1,0 +1,55 @@
+"""FP64 oracle of the geometric phase rotation applied at visibility load.
+
+TEST INFRASTRUCTURE ONLY, like the rest of ``oracle/``: only the test suite,
+the package smoke check and the benchmark's CPU-baseline leg may import it.
+
+Sec. 4.2 (iii): correlation yields visibilities phase-centred at zenith;
+for an instrument with a smaller field of view a geometric phase factor
+rotates them to the pointing centre before imaging. Readings used here:
+
+* the new phase centre is given by its direction cosines (l0, m0) relative
+  to zenith, n0 = sqrt(1 - l0^2 - m0^2);
+* a source in direction (l, m, n) contributes exp(-2 pi i (u l + v m +
+  w (n - 1)) / lambda) to a zenith-centred visibility (the sign of Eq. 5,
+  with the w term kept), so the rotation multiplies every visibility by
+  exp(+2 pi i (u l0 + v m0 + w (n0 - 1)) nu / c), which turns a source at
+  the new centre into a constant;
+* (u, v, w) are not re-projected: the image stays on the zenith tangent
+  plane, shifted so that the new centre is at its middle;
+* the factor multiplies V' after the gains (both are per-visibility
+  scalars, so their order does not matter).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .blink_oracle import C_LIGHT, image_one
+
+
+def geometric_delay(uvw_m, l0: float, m0: float):
+    """u l0 + v m0 + w (n0 - 1) in metres for uvw [..., 3]."""
+    uvw = np.asarray(uvw_m, dtype=np.float64)
+    n0 = np.sqrt(1.0 - l0 * l0 - m0 * m0)
+    return uvw[..., 0] * l0 + uvw[..., 1] * m0 + uvw[..., 2] * (n0 - 1.0)
+
+
+def rotate(vis, uvw_m, freq_hz: float, l0: float, m0: float):
+    """V exp(+2 pi i d nu / c) for one channel (vis and uvw over the same baselines)."""
+    d = geometric_delay(uvw_m, l0, m0)
+    return np.asarray(vis, dtype=np.complex128) * np.exp(2j * np.pi * d * (np.float64(freq_hz) / C_LIGHT))
+
+
+def image_batch_rotated(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, weighting, norm, l0, m0,
+                        flags=None, gains=None, ant1=None, ant2=None, images=None):
+    """Images [len][M][M] and W [len] with the phase centre rotated to (l0, m0)."""
+    T, C, B = vis.shape
+    idx = range(T * C) if images is None else list(images)
+    out, ws = [], []
+    for i in idx:
+        t, c = divmod(int(i), C)
+        v = rotate(vis[t, c], uvw_m[t], freq_hz[c], l0, m0)
+        r = image_one(v, uvw_m[t, :, 0], uvw_m[t, :, 1], freq_hz[c], grid_n, pixscale, out_n, weighting,
+                      norm, None if flags is None else flags[t], gains, ant1, ant2)
+        out.append(r["image"])
+        ws.append(r["W"])
+    return np.stack(out), np.asarray(ws)

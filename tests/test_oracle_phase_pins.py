@@ -1,0 +1,68 @@
+"""Pins of the phase-rotation oracle.
+
+* rotating to zenith (0, 0) changes nothing;
+* a source exactly at the new centre, with the w term, becomes a constant
+  visibility, so its image peaks at the centre with its flux;
+* for a coplanar array (w = 0) a source at (l1, m1) moves to the pixel of
+  (l1 - l0, m1 - m0) (point-source placement of the imaging oracle);
+* the delay is the dot product of the baseline with s0 - z (a brute-force
+  check of the n0 - 1 term).
+"""
+import numpy as np
+
+import oracle
+from oracle import phase_rotation as pr
+
+
+def _array(seed, nb=300, w_scale=0.0):
+    rng = np.random.default_rng(seed)
+    uvw = np.zeros((nb, 3))
+    uvw[:, 0] = rng.uniform(-12, 12, nb)
+    uvw[:, 1] = rng.uniform(-12, 12, nb)
+    uvw[:, 2] = rng.uniform(-1, 1, nb) * w_scale
+    return uvw
+
+
+def test_zenith_is_identity():
+    uvw = _array(1, w_scale=5.0)
+    v = np.exp(1j * np.linspace(0, 3, len(uvw)))
+    assert np.array_equal(pr.rotate(v, uvw, 1.5e8, 0.0, 0.0), v.astype(np.complex128))
+
+
+def test_source_at_new_centre_becomes_constant():
+    uvw = _array(2, w_scale=8.0)
+    l0, m0 = 0.21, -0.13
+    n0 = np.sqrt(1 - l0 ** 2 - m0 ** 2)
+    freq = 1.7e8
+    lam = oracle.C_LIGHT / freq
+    v = 3.0 * np.exp(-2j * np.pi * (uvw[:, 0] * l0 + uvw[:, 1] * m0 + uvw[:, 2] * (n0 - 1)) / lam)
+    r = pr.rotate(v, uvw, freq, l0, m0)
+    assert np.allclose(r, 3.0, rtol=0, atol=1e-9)
+    n = 64
+    img = oracle.image_one(r, uvw[:, 0], uvw[:, 1], freq, n, lam / (3 * 24.0) / lam, n, oracle.NATURAL,
+                           oracle.NORM_WEIGHTS)["image"]
+    assert np.unravel_index(np.argmax(img), img.shape) == (n // 2, n // 2)
+    assert abs(img[n // 2, n // 2] - 3.0) <= 1e-9
+
+
+def test_coplanar_shift_moves_source_by_the_rotation():
+    uvw = _array(3)
+    freq = oracle.C_LIGHT                      # lambda = 1 m: u in wavelengths = metres
+    n, pix = 64, 1.0 / (3 * 24.0)
+    l1, m1 = 12 * pix, -5 * pix                # source 12 pixels right, 5 down of zenith
+    l0, m0 = 4 * pix, 3 * pix                  # new centre
+    v = np.exp(-2j * np.pi * (uvw[:, 0] * l1 + uvw[:, 1] * m1))
+    r = pr.rotate(v, uvw, freq, l0, m0)
+    img = oracle.image_one(r, uvw[:, 0], uvw[:, 1], freq, n, pix, n, oracle.NATURAL,
+                           oracle.NORM_WEIGHTS)["image"]
+    assert np.unravel_index(np.argmax(img), img.shape) == (n // 2 - 8, n // 2 + 8)
+
+
+def test_delay_is_baseline_dot_direction_change():
+    uvw = _array(4, w_scale=3.0)
+    l0, m0 = -0.3, 0.4
+    s0 = np.array([l0, m0, np.sqrt(1 - l0 ** 2 - m0 ** 2)])
+    z = np.array([0.0, 0.0, 1.0])
+    for b in range(0, len(uvw), 37):
+        ref = sum(uvw[b, k] * (s0[k] - z[k]) for k in range(3))
+        assert abs(pr.geometric_delay(uvw[b], l0, m0) - ref) <= 1e-12
