@@ -28,6 +28,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
 KB_SUPPORT = 6                 # Kaiser-Bessel support (cells) of the kernel-gridding workload
+ROT_LM = (0.05, 0.03)          # phase centre of the rotation workload (direction cosines)
 METRIC = "dirty images/s and visibilities/s at 128 tiles, 1024² grid; % HBM roofline"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_grid_cols_rows_widefield1024.json")
 CSRC = os.path.join(ROOT, "paper_2405_13478_amd", "csrc")
@@ -243,7 +244,7 @@ def summarize(out_dir):
 def _setup(args, synth):
     """(workload, timesteps per step, channels per step) for --workload."""
     k = args.workload
-    if k in ("widefield", "widefield_kb"):
+    if k in ("widefield", "widefield_kb", "widefield_rot"):
         TT = args.timesteps_per_step or 10
         return synth.widefield(n_time=max(TT, args.timesteps or 100), n_chan=768), TT
     if k == "plain":
@@ -259,6 +260,7 @@ def _setup(args, synth):
 
 DESCRIPTION = {
     "widefield": "widefield 128 tiles (8128 baselines), 768 ch x 100 timesteps, 1024^2 grid -> 512^2 cutout, natural weighting",
+    "widefield_rot": "widefield 128 tiles (8128 baselines), 768 ch x 100 timesteps, 1024^2 grid -> 512^2 cutout, natural weighting, phase centre rotated to (l, m) = (0.05, 0.03) at load",
     "widefield_kb": "widefield 128 tiles (8128 baselines), 768 ch x 100 timesteps, 1024^2 grid -> 512^2 cutout, natural weighting, Kaiser-Bessel gridding kernel of 6 cells with taper correction",
     "plain": "plain single image, 32 antennas (496 baselines), 1 ch at 160 MHz, 128^2, natural weighting",
     "allsky": "station all-sky, 256 antennas (32640 baselines), 32 ch x 1000 timesteps (32,000 images), 180^2, uniform weighting, 2-10% flagged per timestep",
@@ -319,6 +321,7 @@ def bench_images(args, np, torch, blink, synth, dev):
     n_img = TT * w.n_chan
     M, N, H, B = w.out_n, w.grid_n, w.grid_n // 2, w.n_bl
     ksup = KB_SUPPORT if args.workload == "widefield_kb" else 0
+    plm = ROT_LM if args.workload == "widefield_rot" else (0.0, 0.0)
     images = torch.empty((n_img, M, M), dtype=torch.float32, device=dev)   # reused per step
     ws_cache = {}
 
@@ -330,7 +333,7 @@ def bench_images(args, np, torch, blink, synth, dev):
                                      args.cols_per_wg, args.rows_wg)
         tunings[vbytes] = tun
         p = blink.blink.make_problem(v[:TT], uvw[:TT], freq, N, w.pixscale, M, w.weighting, w.norm,
-                                     None, **tun, kernel_support=ksup)
+                                     None, **tun, kernel_support=ksup, phase_lm=plm)
         ws_cache[vbytes] = ws = blink.workspace(p, blink.CALL_IMAGE, dev)
 
         def run(k, tm):
@@ -338,7 +341,8 @@ def bench_images(args, np, torch, blink, synth, dev):
             sl = slice(b * TT, (b + 1) * TT)
             blink.image_batch(v[sl], uvw[sl], freq, grid_n=N, pixscale=w.pixscale, out_n=M,
                               weighting=w.weighting, norm=w.norm, flags=None if flags is None else flags[sl],
-                              vis_scale=scale, images=images, ws=ws, times=tm, **tun, kernel_support=ksup)
+                              vis_scale=scale, images=images, ws=ws, times=tm, **tun, kernel_support=ksup,
+                              phase_lm=plm)
         return run
 
     ncz = np.concatenate([nonzero_columns(w, slice(b * TT, (b + 1) * TT))
@@ -438,7 +442,7 @@ def bench_images(args, np, torch, blink, synth, dev):
     if args.workload == "plain":
         out["latency_us_per_image"] = round(res["ms_per_step"] * 1e3, 2)
 
-    sample_n = args.cpu_sample if args.cpu_sample is not None else {"widefield": 128, "widefield_kb": 32, "plain": 64, "allsky": 4096, "precision": 16}[args.workload]
+    sample_n = args.cpu_sample if args.cpu_sample is not None else {"widefield": 128, "widefield_kb": 32, "widefield_rot": 0, "plain": 64, "allsky": 4096, "precision": 16}[args.workload]
     if not args.no_cpu_baseline and sample_n > 0:
         cores = max(1, min(16, os.cpu_count() or 1))
         S = min(sample_n, w.n_img)
@@ -625,8 +629,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="widefield",
-                    choices=("widefield", "widefield_kb", "plain", "allsky", "diff", "precision", "dynspec",
-                             "xengine"))
+                    choices=("widefield", "widefield_kb", "widefield_rot", "plain", "allsky", "diff", "precision",
+                             "dynspec", "xengine"))
     ap.add_argument("--timesteps-per-step", type=int, default=None)
     ap.add_argument("--timesteps", type=int, default=None,
                     help="timesteps of the job generated into HBM (default: the whole widefield job)")
@@ -649,7 +653,8 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "images shard across GPUs with no exchange, see DESIGN.md", file=sys.stderr)
         sys.exit(2)
-    defaults = {"widefield": (20, 3), "widefield_kb": (10, 2), "plain": (500, 20), "allsky": (3, 1),
+    defaults = {"widefield": (20, 3), "widefield_kb": (10, 2), "widefield_rot": (20, 3), "plain": (500, 20),
+                "allsky": (3, 1),
                 "diff": (5, 2), "precision": (5, 1), "dynspec": (10, 2), "xengine": (10, 2)}
     ds, dw = defaults[args.workload]
     args.steps = ds if args.steps is None else args.steps

@@ -66,6 +66,14 @@
  *   the FP64 distances; blink_grid returns counts of contributions per cell.
  *   Uniform weighting and blink_degrid_adjoint with a kernel return
  *   BLINK_E_UNSUPPORTED.
+ * - Phase rotation (phase_l, phase_m != 0; Sec. 4.2 (iii)): correlation
+ *   phases the visibilities to zenith; each V' is multiplied by
+ *   exp(+2 pi i (u l0 + v m0 + w (n0 - 1)) nu_c / c0), n0 = sqrt(1 - l0^2 -
+ *   m0^2), so that a source at (l0, m0) becomes a constant and images at the
+ *   centre. (u, v, w) are not re-projected: the image stays on the zenith
+ *   tangent plane, shifted by (l0, m0). The delay is formed in double at the
+ *   sort, the phase in cycles in double, its sine and cosine in float.
+ *   blink_degrid_adjoint with a rotation returns BLINK_E_UNSUPPORTED.
  */
 #ifndef BLINK_H
 #define BLINK_H
@@ -121,6 +129,9 @@ typedef struct {
                          /* with the image-domain correction (see below)               */
   double  kernel_beta;   /* Kaiser-Bessel shape; < 0 = pi sqrt(0.5625 W^2 - 0.8)       */
                          /* (needs W >= 2); ignored when kernel_support = 0            */
+  double  phase_l;       /* phase centre (direction cosines relative to zenith) for    */
+  double  phase_m;       /* the geometric rotation at load; (0, 0) = zenith, none;     */
+                         /* l^2 + m^2 < 1                                               */
 } blink_problem;
 
 typedef struct {          /* device pointers; the optional ones may be NULL            */

@@ -47,7 +47,7 @@ class Problem(ctypes.Structure):
                 ("norm", ctypes.c_int32), ("vis_type", ctypes.c_int32),
                 ("chunk_images", ctypes.c_int32), ("cols_per_wg", ctypes.c_int32),
                 ("rows_wg", ctypes.c_int32), ("kernel_support", ctypes.c_int32),
-                ("kernel_beta", ctypes.c_double)]
+                ("kernel_beta", ctypes.c_double), ("phase_l", ctypes.c_double), ("phase_m", ctypes.c_double)]
 
 
 class Inputs(ctypes.Structure):
@@ -141,7 +141,7 @@ def _check(code, what):
 
 def make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n=None, weighting=NATURAL,
                  norm=NORM_WEIGHTS, gains=None, chunk_images=0, cols_per_wg=0, rows_wg=0,
-                 kernel_support=0, kernel_beta=-1.0) -> Problem:
+                 kernel_support=0, kernel_beta=-1.0, phase_lm=(0.0, 0.0)) -> Problem:
     if vis.dtype == torch.complex64:
         T, C, B = vis.shape
         vt = VIS_C64
@@ -157,7 +157,7 @@ def make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n=None, weighting=NA
                    pixscale=float(pixscale), weighting=int(weighting), norm=int(norm),
                    vis_type=vt, chunk_images=int(chunk_images), cols_per_wg=int(cols_per_wg),
                    rows_wg=int(rows_wg), kernel_support=int(kernel_support),
-                   kernel_beta=float(kernel_beta))
+                   kernel_beta=float(kernel_beta), phase_l=float(phase_lm[0]), phase_m=float(phase_lm[1]))
 
 
 def make_inputs(p: Problem, vis, uvw_m, freq_hz, flags=None, vis_scale=None, ant1=None,
@@ -202,12 +202,13 @@ def _vis_type(vis):
 def image_batch(vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None, weighting=NATURAL,
                 norm=NORM_WEIGHTS, flags=None, vis_scale=None, ant1=None, ant2=None, gains=None,
                 chunk_images=None, cols_per_wg=None, rows_wg=None, images=None, weight_sum=None,
-                ws=None, stream=None, times=None, kernel_support=0, kernel_beta=-1.0):
+                ws=None, stream=None, times=None, kernel_support=0, kernel_beta=-1.0, phase_lm=(0.0, 0.0)):
     """Dirty images [T*C][M][M] float32 of the cube (blink_image_batch).
 
     Tunables left as None come from the autotuner's cache for this shape.
     ``kernel_support`` W >= 1 grids with a Kaiser-Bessel kernel of W cells
     (shape ``kernel_beta``, < 0 for the default) and corrects the image for it.
+    ``phase_lm`` = (l0, m0) rotates the phase centre from zenith to that direction.
     With ``times`` (a KernelTimes) the instrumented twin blink_image_batch_timed
     runs instead: same results, per-kernel-class event timings, host waits.
     """
@@ -215,7 +216,7 @@ def image_batch(vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None, weighting=
     M = grid_n if out_n is None else out_n
     tun = tuning_for(grid_n, M, vis.shape[2], weighting, _vis_type(vis), chunk_images, cols_per_wg, rows_wg)
     p = make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, weighting, norm, gains, **tun,
-                     kernel_support=kernel_support, kernel_beta=kernel_beta)
+                     kernel_support=kernel_support, kernel_beta=kernel_beta, phase_lm=phase_lm)
     inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains)
     n_img, M = p.n_time * p.n_chan, p.out_n
     if images is None:
@@ -235,11 +236,11 @@ def image_batch(vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None, weighting=
 
 def grid(vis, uvw_m, freq_hz, *, grid_n, pixscale, weighting=NATURAL, flags=None, vis_scale=None,
          ant1=None, ant2=None, gains=None, counts=True, chunk_images=0, stream=None,
-         kernel_support=0, kernel_beta=-1.0):
+         kernel_support=0, kernel_beta=-1.0, phase_lm=(0.0, 0.0)):
     """(weighted grid [T*C][N][N] c64, counts int32 or None, W float32, n_dropped int32)."""
     lib = load_library()
     p = make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, grid_n, weighting, NORM_NONE, gains,
-                     chunk_images, kernel_support=kernel_support, kernel_beta=kernel_beta)
+                     chunk_images, kernel_support=kernel_support, kernel_beta=kernel_beta, phase_lm=phase_lm)
     inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains)
     n_img, N, dev = p.n_time * p.n_chan, grid_n, vis.device
     g = torch.empty((n_img, N, N), dtype=torch.complex64, device=dev)

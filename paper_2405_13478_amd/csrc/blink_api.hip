@@ -36,6 +36,9 @@ inline size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int KB_MAX_SUPPORT = 16;
 
+// A phase centre other than zenith asks for the geometric rotation.
+inline bool rotates(const blink_problem* p) { return p->phase_l != 0.0 || p->phase_m != 0.0; }
+
 // pi sqrt(0.5625 W^2 - 0.8): the Kaiser-Bessel shape for a grid twice the
 // kept image (Beatty, Nishimura and Pauly 2005); negative when W is too small.
 double kb_default_beta(int w) {
@@ -62,6 +65,7 @@ struct Work {
   double* su;
   double* sv;
   int* perm;
+  double* sd;         // sorted geometric delays, only with a phase rotation
   int* bnd;
   int* ncz;
   int* wpart;
@@ -100,6 +104,7 @@ size_t carve(const blink_problem* p, int call, int chunk, char* base, Work* w) {
   x.su = (double*)take(T * B * 8);
   x.sv = (double*)take(T * B * 8);
   x.perm = (int*)take(T * B * 4);
+  if (rotates(p)) x.sd = (double*)take(T * B * 8);
   const size_t n_img = (size_t)p->n_time * (size_t)p->n_chan;
   x.bnd = (int*)take(n_img * (N + 2) * 4);
   x.ncz = (int*)take(n_img * 4);
@@ -128,6 +133,9 @@ blink_status validate_problem(const blink_problem* p, int call) {
     return BLINK_E_ARG;
   if (p->rows_wg < 0) return BLINK_E_ARG;
   if (p->kernel_support < 0 || p->kernel_support > KB_MAX_SUPPORT) return BLINK_E_ARG;
+  if (!isfinite(p->phase_l) || !isfinite(p->phase_m) ||
+      !(p->phase_l * p->phase_l + p->phase_m * p->phase_m < 1.0))
+    return BLINK_E_ARG;
   if (p->kernel_support > 0) {
     if (!isfinite(p->kernel_beta)) return BLINK_E_ARG;
     if (p->kernel_beta < 0 && kb_default_beta(p->kernel_support) < 0) return BLINK_E_ARG;
@@ -144,6 +152,7 @@ blink_status validate_problem(const blink_problem* p, int call) {
   if (call == BLINK_CALL_ADJOINT && p->vis_type != BLINK_VIS_C64) return BLINK_E_UNSUPPORTED;
   if (p->kernel_support > 0 && (p->weighting != BLINK_NATURAL || call == BLINK_CALL_ADJOINT))
     return BLINK_E_UNSUPPORTED;
+  if (rotates(p) && call == BLINK_CALL_ADJOINT) return BLINK_E_UNSUPPORTED;
   return BLINK_OK;
 }
 
@@ -229,6 +238,12 @@ void run_sort(const blink_problem* p, const blink_inputs* in, const Work& w, hip
   s.idx[0] = w.idx[0]; s.idx[1] = w.idx[1];
   s.n_unflagged = w.counters; s.n_valid = w.counters + T;
   s.su = w.su; s.sv = w.sv; s.perm = w.perm;
+  s.sd = w.sd;
+  if (w.sd != nullptr) {
+    s.pl = p->phase_l;
+    s.pm = p->phase_m;
+    s.pn1 = sqrt(1.0 - p->phase_l * p->phase_l - p->phase_m * p->phase_m) - 1.0;
+  }
   if (B == 0 || B > SORT_RUN) {
     T_.begin(0);
     hipLaunchKernelGGL(k_sort_init, dim3(cdiv(2LL * T, 256)), dim3(256), 0, st, w.counters, 2 * T);
@@ -273,7 +288,7 @@ ImgArgs make_args(const blink_problem* p, const blink_inputs* in, const Work& w)
   a.ant1 = in->ant1; a.ant2 = in->ant2;
   a.gains = reinterpret_cast<const float2*>(in->gains);
   a.n_ant = p->n_ant;
-  a.su = w.su; a.sv = w.sv; a.perm = w.perm;
+  a.su = w.su; a.sv = w.sv; a.perm = w.perm; a.sd = w.sd;
   a.n_unflagged = w.counters; a.n_valid = w.counters + p->n_time;
   a.bnd = w.bnd; a.ncz = w.ncz; a.wpart = w.wpart; a.kpart = w.kpart; a.wstride = w.wstride;
   a.half = w.half; a.gamma = w.gamma; a.pacc = w.pacc;

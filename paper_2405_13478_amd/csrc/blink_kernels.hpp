@@ -61,7 +61,15 @@ struct SortArgs {
   double* su;                    // [T][B] sorted u
   double* sv;                    // [T][B] v in the same order
   int* perm;                     // [T][B] baseline index in the same order
+  double* sd;                    // [T][B] geometric delay in the same order, or null (no rotation)
+  double pl, pm, pn1;            // phase centre l0, m0 and n0 - 1
 };
+
+// u l0 + v m0 + w (n0 - 1): the path difference (metres) between the new
+// phase centre and zenith for baseline uvw.
+__device__ __forceinline__ double geo_delay(const double* uvw, double l0, double m0, double n1) {
+  return uvw[0] * l0 + uvw[1] * m0 + uvw[2] * n1;
+}
 
 __global__ void k_sort_init(int* a, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -175,6 +183,7 @@ __global__ void __launch_bounds__(1024) k_sort_small(SortArgs a) {
     const int b = si[j];
     a.su[tb + j] = a.uvw[(tb + b) * 3 + 0];
     a.sv[tb + j] = a.uvw[(tb + b) * 3 + 1];
+    if (a.sd != nullptr) a.sd[tb + j] = geo_delay(a.uvw + (tb + b) * 3, a.pl, a.pm, a.pn1);
     a.perm[tb + j] = b;
   }
   if (threadIdx.x == 0) {
@@ -222,6 +231,7 @@ __global__ void __launch_bounds__(256) k_sort_finish(SortArgs a, int src) {
   const int b = a.idx[src][tb + j];
   a.su[tb + j] = a.uvw[(tb + b) * 3 + 0];
   a.sv[tb + j] = a.uvw[(tb + b) * 3 + 1];
+  if (a.sd != nullptr) a.sd[tb + j] = geo_delay(a.uvw + (tb + b) * 3, a.pl, a.pm, a.pn1);
   a.perm[tb + j] = b;
   const bool valid = k != KEY_MAX;
   const bool next_invalid = (j + 1 == a.B) || a.key[src][tb + j + 1] == KEY_MAX;
@@ -241,6 +251,7 @@ struct ImgArgs {
   const double* su;             // [T][B]
   const double* sv;             // [T][B]
   const int* perm;              // [T][B]
+  const double* sd;             // [T][B] sorted geometric delays (metres) or null: no rotation
   const int* n_valid;           // [T]
   const int* n_unflagged;       // [T]
   int* bnd;                     // [T*C][N + 2]
@@ -362,6 +373,17 @@ __device__ __forceinline__ float2 load_vis(const ImgArgs& a, size_t off, int b, 
   return v;
 }
 
+// Geometric phase rotation of a visibility: V exp(+2 pi i d nu / c) for the
+// delay d (metres) of its baseline. The phase in cycles is formed in double
+// and reduced to [-1/2, 1/2] before the single-precision sine and cosine.
+__device__ __forceinline__ float2 rotate_phase(float2 v, double d, double f) {
+  const double cyc = d * (f / C_LIGHT);
+  const float fr = (float)(cyc - rint(cyc));
+  float sn, cs;
+  sincospif(2.0f * fr, &sn, &cs);
+  return make_float2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
+}
+
 // Grid the column's entries: sorted positions [dlo, dhi) add V' at row i_v,
 // positions [clo, chi) (the mirror column) add conj(V') at row -i_v. Both
 // ranges are walked as one list, GU x 64 entries per step: every step first
@@ -380,6 +402,7 @@ struct ColSpan {                 // the sorted entries of one u-cell column
 
 struct EntryStep {               // GU x 64 entries in registers
   double sv[GU];
+  double dl[GU];                 // geometric delay (phase rotation only)
   int bl[GU];
   int row[GU];
   float2 val[GU];
@@ -399,6 +422,7 @@ __device__ __forceinline__ void step_keys(const ImgArgs& a, const ColSpan& c, in
     const int j = e.cj[u] ? c.clo + (i - nd) : c.dlo + i;
     e.sv[u] = e.ok[u] ? a.sv[tb + j] : 0.0;
     e.bl[u] = e.ok[u] ? a.perm[tb + j] : 0;
+    e.dl[u] = (a.sd != nullptr && e.ok[u]) ? a.sd[tb + j] : 0.0;
   }
 }
 
@@ -414,6 +438,7 @@ __device__ __forceinline__ void step_gather(const ImgArgs& a, int t, int ch, dou
     if (e.cj[u]) r = -r;
     e.row[u] = r < 0 ? r + N : r;
     e.val[u] = e.ok[u] ? load_vis(a, vb + e.bl[u], e.bl[u], ch) : make_float2(0.f, 0.f);
+    if (a.sd != nullptr) e.val[u] = rotate_phase(e.val[u], e.dl[u], a.freq[ch]);
   }
 }
 
@@ -507,6 +532,7 @@ __device__ __forceinline__ void grid_steps_kb(const ImgArgs& a, const ColSpan& s
     const double du = (double)c - xu;
     if (ok && fabs(du) <= hw) {
       float2 v = load_vis(a, vb + b, b, ch);
+      if (a.sd != nullptr) v = rotate_phase(v, a.sd[tb + j], a.freq[ch]);
       if (cj) v.y = -v.y;
       const float wu = kb_weight((float)du, a);
       const int j0 = (int)ceil(xv - hw), j1 = (int)floor(xv + hw);

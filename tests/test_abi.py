@@ -83,6 +83,8 @@ def _image(lib, p, inp, images=FAKE, ws=None, nbytes=0):
     (dict(kernel_support=4, kernel_beta=float("nan")), E_ARG),
     (dict(kernel_support=4, kernel_beta=float("inf")), E_ARG),
     (dict(kernel_support=4, kernel_beta=-1.0, weighting=1), E_UNSUP),   # natural weighting only
+    (dict(phase_l=float("nan")), E_ARG), (dict(phase_l=0.8, phase_m=0.6), E_ARG),   # needs l^2 + m^2 < 1
+    (dict(phase_m=float("inf")), E_ARG),
 ])
 def test_problem_validation(lib, kw, code):
     assert _image(lib, _prob(**kw), _inputs()) == code
@@ -194,3 +196,15 @@ def test_correlate_validation(lib):
     assert c(FAKE, 1, 1, 8, 32, None, None, None) == E_ARG
     assert c(ctypes.c_void_p(0x100008), 1, 1, 8, 32, FAKE, None, None) == E_ARG   # misaligned
     assert c(None, 0, 4, 8, 32, None, None, None) == E_OK                # empty
+
+
+def test_phase_rotation_has_no_adjoint(lib):
+    p = _prob(phase_l=0.1, phase_m=-0.2)
+    a = lib.blink_degrid_adjoint
+    assert a(ctypes.byref(p), ctypes.byref(_inputs()), FAKE, FAKE, None, None, 0, None) == E_UNSUP
+
+
+def test_phase_rotation_workspace_holds_delays(lib):
+    p0 = _prob(n_bl=1000)
+    p1 = _prob(n_bl=1000, phase_l=0.1)
+    assert lib.blink_workspace_size(ctypes.byref(p1), 1) >= lib.blink_workspace_size(ctypes.byref(p0), 1) + 2 * 1000 * 8
