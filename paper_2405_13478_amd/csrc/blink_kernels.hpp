@@ -410,6 +410,8 @@ struct EntryStep {               // GU x 64 entries in registers
 };
 
 // phase 1: sorted-list loads (v in metres and baseline index) of the step at i0
+// (ROT: and the geometric delays for the phase rotation)
+template <bool ROT>
 __device__ __forceinline__ void step_keys(const ImgArgs& a, const ColSpan& c, int i0, int t, int lane,
                                           EntryStep& e) {
   const size_t tb = (size_t)t * a.B;
@@ -422,12 +424,12 @@ __device__ __forceinline__ void step_keys(const ImgArgs& a, const ColSpan& c, in
     const int j = e.cj[u] ? c.clo + (i - nd) : c.dlo + i;
     e.sv[u] = e.ok[u] ? a.sv[tb + j] : 0.0;
     e.bl[u] = e.ok[u] ? a.perm[tb + j] : 0;
-    e.dl[u] = (a.sd != nullptr && e.ok[u]) ? a.sd[tb + j] : 0.0;
+    if (ROT) e.dl[u] = e.ok[u] ? a.sd[tb + j] : 0.0;
   }
 }
 
 // phase 2: cell rows (FP64) and the visibility gathers of the kept entries
-template <int N>
+template <int N, bool ROT>
 __device__ __forceinline__ void step_gather(const ImgArgs& a, int t, int ch, double s, EntryStep& e) {
   const size_t vb = ((size_t)t * a.C + ch) * a.B;
 #pragma unroll
@@ -438,7 +440,7 @@ __device__ __forceinline__ void step_gather(const ImgArgs& a, int t, int ch, dou
     if (e.cj[u]) r = -r;
     e.row[u] = r < 0 ? r + N : r;
     e.val[u] = e.ok[u] ? load_vis(a, vb + e.bl[u], e.bl[u], ch) : make_float2(0.f, 0.f);
-    if (a.sd != nullptr) e.val[u] = rotate_phase(e.val[u], e.dl[u], a.freq[ch]);
+    if (ROT) e.val[u] = rotate_phase(e.val[u], e.dl[u], a.freq[ch]);
   }
 }
 
@@ -461,17 +463,24 @@ __device__ __forceinline__ void step_add(const EntryStep& e, float2* buf, int* c
 }
 
 // All steps of a column from step i0 on; returns the kept direct and
-// conjugate entries (added to kd / kc).
-template <int N, bool COUNT>
-__device__ __forceinline__ void grid_steps(const ImgArgs& a, const ColSpan& c, int i0, float2* buf, int* cnt,
-                                           int t, int ch, double s, int lane, int& kd, int& kc) {
+// conjugate entries (added to kd / kc). The phase-rotated form is a separate
+// copy of the loop, so the plain one carries none of its work.
+template <int N, bool COUNT, bool ROT>
+__device__ __forceinline__ void grid_steps_t(const ImgArgs& a, const ColSpan& c, int i0, float2* buf, int* cnt,
+                                             int t, int ch, double s, int lane, int& kd, int& kc) {
   const int total = c.total();
   for (; i0 < total; i0 += GU * WAVE) {
     EntryStep e;
-    step_keys(a, c, i0, t, lane, e);
-    step_gather<N>(a, t, ch, s, e);
+    step_keys<ROT>(a, c, i0, t, lane, e);
+    step_gather<N, ROT>(a, t, ch, s, e);
     step_add<COUNT>(e, buf, cnt, kd, kc);
   }
+}
+template <int N, bool COUNT>
+__device__ __forceinline__ void grid_steps(const ImgArgs& a, const ColSpan& c, int i0, float2* buf, int* cnt,
+                                           int t, int ch, double s, int lane, int& kd, int& kc) {
+  if (a.sd != nullptr) grid_steps_t<N, COUNT, true>(a, c, i0, buf, cnt, t, ch, s, lane, kd, kc);
+  else grid_steps_t<N, COUNT, false>(a, c, i0, buf, cnt, t, ch, s, lane, kd, kc);
 }
 
 // ------------------------------------------------------------- kernel gridding
