@@ -401,6 +401,157 @@ __device__ __forceinline__ void wave_fft_emit(float2* buf, int lane, const float
   }
 }
 
+// ------------------------------------------------- half-length exchange
+// The same transform with every stage-to-stage exchange passing through a
+// buffer of N/2 points (padded) instead of N, in two rounds: the outputs of
+// index below N/2 first, then the rest. A Stockham stage's output
+// y[(j / NS) NS R + (j mod NS) + r NS] lies below N/2 exactly when its
+// butterfly j is below NB / 2 (NS R divides N/2 for every stage but the last),
+// and the next stage's input x[j + r N/R] lies below N/2 exactly when r < R/2.
+// So each round writes the outputs of one half of the butterflies and reads
+// one half of every next butterfly's inputs; the lower-half writes and the
+// upper-half reads are at padded index minus pad(N/2), which is a
+// compile-time offset on the read side. Halving the LDS of a transform lets
+// twice as many wavefronts share a CU; the arithmetic and its order are those
+// of the full-buffer stages.
+__host__ __device__ constexpr bool plan_even(int n) {
+  if (n < 2 || n % 32 != 0) return false;
+  while (n > 1) {
+    const int r = pick_radix(n);
+    if (r == 0 || r % 2 != 0) return false;
+    n /= r;
+  }
+  return true;
+}
+
+// Twiddle and DFT of the butterflies held in registers (no LDS traffic).
+template <int N, int R, int NS, int SIGN>
+__device__ __forceinline__ void stage_compute(int lane, const float2* __restrict__ tw,
+                                              float2 (&v)[(N / R + WAVE - 1) / WAVE][R]) {
+  constexpr int NB = N / R;
+  constexpr int PER = (NB + WAVE - 1) / WAVE;
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int j = lane + p * WAVE;
+    if (NB % WAVE == 0 || j < NB) {
+      if constexpr (NS > 1) {
+        constexpr int TW0 = tw_entries_before(N, NS);
+        const float2* t1 = tw + TW0 + j % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = t1[(r - 1) * NS];
+          if (SIGN < 0) w.y = -w.y;
+          v[p][r] = cmul(v[p][r], w);
+        }
+      }
+      dft<R, SIGN>(v[p]);
+    }
+  }
+}
+
+// Round HF of a stage's writes: outputs of the butterflies j in
+// [HF NB/2, (HF + 1) NB/2) to hbuf at padded index - HF pad(N/2).
+template <int N, int R, int NS, int HF>
+__device__ __forceinline__ void half_write(float2* hbuf, int lane, const float2 (&v)[(N / R + WAVE - 1) / WAVE][R]) {
+  constexpr int NB = N / R;
+  constexpr int PER = (NB + WAVE - 1) / WAVE;
+  constexpr int HB = NB / 2;
+  constexpr int PH = pad(N / 2);
+  constexpr bool WR_LIN = NS % 16 == 0 || (NS == 1 && 16 % R == 0);
+  constexpr int WR_STEP = NS == 1 ? 1 : NS + NS / 16;
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int j = lane + p * WAVE;
+    bool in;
+    if constexpr (HB % WAVE == 0) in = HF == 0 ? p * WAVE < HB : p * WAVE >= HB;   // whole registers
+    else in = HF == 0 ? j < HB : (j >= HB && j < NB);
+    if (in) {
+      const int base = (j / NS) * NS * R + j % NS;
+      if constexpr (WR_LIN) {
+        const int b = pad(base) - HF * PH;
+#pragma unroll
+        for (int r = 0; r < R; ++r) hbuf[b + r * WR_STEP] = v[p][r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) hbuf[pad(base + r * NS) - HF * PH] = v[p][r];
+      }
+    }
+  }
+}
+
+// Round HF of a stage's reads: inputs r in [HF R/2, (HF + 1) R/2).
+template <int N, int R, int HF>
+__device__ __forceinline__ void half_read(const float2* hbuf, int lane, float2 (&v)[(N / R + WAVE - 1) / WAVE][R]) {
+  constexpr int NB = N / R;
+  constexpr int PER = (NB + WAVE - 1) / WAVE;
+  constexpr bool RD_LIN = NB % 16 == 0;
+  constexpr int RD_STEP = NB + NB / 16;
+  constexpr int PH = pad(N / 2);
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int j = lane + p * WAVE;
+    if (NB % WAVE == 0 || j < NB) {
+      if constexpr (RD_LIN) {
+        const int b = pad(j);
+#pragma unroll
+        for (int r = HF * R / 2; r < (HF + 1) * R / 2; ++r) v[p][r] = hbuf[b + (r * RD_STEP - HF * PH)];
+      } else {
+#pragma unroll
+        for (int r = HF * R / 2; r < (HF + 1) * R / 2; ++r) v[p][r] = hbuf[pad(j + r * NB) - HF * PH];
+      }
+    }
+  }
+}
+
+// The stages from NS on, given the stage's inputs in v; the last stage hands
+// its outputs to emit(ic<QB>, X) as stockham_last_emit does.
+template <int N, int SIGN, int NS, class Emit>
+__device__ __forceinline__ void half_chain(float2* hbuf, int lane, const float2* __restrict__ tw,
+                                           float2 (&v)[(N / pick_radix(N / NS) + WAVE - 1) / WAVE][pick_radix(N / NS)],
+                                           Emit&& emit) {
+  constexpr int R = pick_radix(N / NS);
+  constexpr int PER = (N / R + WAVE - 1) / WAVE;
+  stage_compute<N, R, NS, SIGN>(lane, tw, v);
+  if constexpr (NS * R == N) {
+    static_for<0, PER>([&](auto pc) {
+      constexpr int p = decltype(pc)::value;
+      if ((N / R) % WAVE == 0 || lane + p * WAVE < N / R) {
+        static_for<0, R>([&](auto rc) {
+          constexpr int r = decltype(rc)::value;
+          emit(ic<p * WAVE + r * NS>{}, v[p][r]);
+        });
+      }
+    });
+  } else {
+    constexpr int R2 = pick_radix(N / (NS * R));
+    float2 v2[(N / R2 + WAVE - 1) / WAVE][R2];
+    half_write<N, R, NS, 0>(hbuf, lane, v);
+    wave_sync();
+    half_read<N, R2, 0>(hbuf, lane, v2);
+    wave_sync();
+    half_write<N, R, NS, 1>(hbuf, lane, v);
+    wave_sync();
+    half_read<N, R2, 1>(hbuf, lane, v2);
+    wave_sync();
+    half_chain<N, SIGN, NS * R>(hbuf, lane, tw, v2, emit);
+  }
+}
+
+// Registers of the first stage's inputs: v[p][r] = x[lane + 64 p + r N/R0].
+template <int N>
+struct HalfIn {
+  static constexpr int R = pick_radix(N);
+  static constexpr int PER = (N / R + WAVE - 1) / WAVE;
+  float2 v[PER][R];
+};
+
+template <int N, int SIGN, class Emit>
+__device__ __forceinline__ void wave_fft_half_emit(float2* hbuf, int lane, const float2* __restrict__ tw,
+                                                   HalfIn<N>& in, Emit&& emit) {
+  static_assert(plan_even(N), "half-length exchange needs even radices");
+  half_chain<N, SIGN, 1>(hbuf, lane, tw, in.v, emit);
+}
+
 template <int N, int SIGN, int NS = 1>
 __device__ __forceinline__ void wave_fft(float2* buf, int lane, const float2* __restrict__ tw) {
   if constexpr (NS < N) {

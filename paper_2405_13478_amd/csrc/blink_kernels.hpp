@@ -718,6 +718,163 @@ __global__ void __launch_bounds__((Cols<N, CPW>::THREADS)) k_grid_cols(ImgArgs a
   }
 }
 
+// ------------------------------------------- column pass, half-length LDS
+// The image-mode column kernel (natural weighting, nearest cell) with every
+// LDS exchange of the column through N/2 points: the rows below N/2 are
+// gridded and handed to the first stage's registers, then the rows above,
+// and the stages exchange in two rounds (wave_fft_half_emit). Each row
+// receives the same adds in the same order as in the full-buffer kernel.
+template <int N, int CPW>
+struct ColsHalf {
+  static constexpr int STRIDE = padded_len(N / 2);
+  static constexpr int THREADS = CPW * WAVE;
+  static constexpr int TW = TwLds<N>::ON ? tw_entries(N) : 0;
+  static constexpr size_t LDS = (size_t)(CPW * STRIDE + TW) * sizeof(float2);
+};
+
+// LDS adds of the kept entries of a step whose row lies in half HF
+template <int N, int HF>
+__device__ __forceinline__ void step_add_half(const EntryStep& e, float2* hbuf) {
+#pragma unroll
+  for (int u = 0; u < GU; ++u) {
+    if (e.ok[u] && (e.row[u] >= N / 2) == (HF == 1)) {
+      float2 v = e.val[u];
+      if (e.cj[u]) v.y = -v.y;
+      float2* p = &hbuf[pad(e.row[u] - HF * (N / 2))];
+      atomicAdd(&p->x, v.x);
+      atomicAdd(&p->y, v.y);
+    }
+  }
+}
+
+__device__ __forceinline__ void step_count(const EntryStep& e, int& kd, int& kc) {
+#pragma unroll
+  for (int u = 0; u < GU; ++u) {
+    kd += __popcll(__ballot(e.ok[u] && !e.cj[u]));
+    kc += __popcll(__ballot(e.ok[u] && e.cj[u]));
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void zero_half(float2* hbuf, int lane) {
+  for (int r = lane; r < padded_len(N / 2); r += WAVE) hbuf[r] = make_float2(0.f, 0.f);
+}
+
+// Grids one column in two halves and loads the first stage's inputs. A
+// column of at most GU x 64 entries (the usual case) keeps its one step of
+// entries in registers for both halves; longer columns load them again.
+template <int N, bool ROT>
+__device__ __forceinline__ void grid_col_half(const ImgArgs& a, const ColSpan& c, float2* hbuf, HalfIn<N>& in,
+                                              int t, int ch, double s, int lane, int& kd, int& kc) {
+  constexpr int R0 = HalfIn<N>::R;
+  const int total = c.total();
+  const bool one = total <= GU * WAVE;
+  EntryStep e;
+  zero_half<N>(hbuf, lane);
+  wave_sync();
+  if (one) {
+    if (total > 0) {
+      step_keys<ROT>(a, c, 0, t, lane, e);
+      step_gather<N, ROT>(a, t, ch, s, e);
+      step_add_half<N, 0>(e, hbuf);
+      step_count(e, kd, kc);
+    }
+  } else {
+    for (int i0 = 0; i0 < total; i0 += GU * WAVE) {
+      EntryStep f;
+      step_keys<ROT>(a, c, i0, t, lane, f);
+      step_gather<N, ROT>(a, t, ch, s, f);
+      step_add_half<N, 0>(f, hbuf);
+      step_count(f, kd, kc);
+    }
+  }
+  wave_sync();
+  half_read<N, R0, 0>(hbuf, lane, in.v);
+  wave_sync();
+  zero_half<N>(hbuf, lane);
+  wave_sync();
+  if (one) {
+    if (total > 0) step_add_half<N, 1>(e, hbuf);
+  } else {
+    for (int i0 = 0; i0 < total; i0 += GU * WAVE) {
+      EntryStep f;
+      step_keys<ROT>(a, c, i0, t, lane, f);
+      step_gather<N, ROT>(a, t, ch, s, f);
+      step_add_half<N, 1>(f, hbuf);
+    }
+  }
+  wave_sync();
+  half_read<N, R0, 1>(hbuf, lane, in.v);
+  wave_sync();
+}
+
+// Same tiling, XCD mapping and outputs as k_grid_cols<N, MODE_IMAGE, false, CPW>.
+template <int N, int CPW>
+__global__ void __launch_bounds__((ColsHalf<N, CPW>::THREADS)) k_grid_cols_half(ImgArgs a) {
+  extern __shared__ float4 lds_raw[];
+  __shared__ int red[2 * CPW];
+  using C_ = ColsHalf<N, CPW>;
+  constexpr int H = N / 2;
+  const int L = blockIdx.x;
+  const int r8 = L >> 3;
+  const int li = (r8 / a.ntiles) * 8 + (L & 7);
+  const int tile = r8 % a.ntiles;
+  if (li >= a.nimg) return;                          // padding of the last group of 8 images
+  float2* lds = reinterpret_cast<float2*>(lds_raw);
+  float2* ltw = lds + CPW * C_::STRIDE;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), lane = threadIdx.x % WAVE;
+  const int img = a.img0 + li;
+  const int t = img / a.C, ch = img - t * a.C;
+  const int c0 = tile * CPW;
+  const int ncols = min(H, a.ncz[img]);
+  if (c0 >= ncols) {                                 // the whole tile is empty
+    if (threadIdx.x == 0) {
+      a.wpart[(size_t)img * a.wstride + tile] = 0;
+      a.kpart[(size_t)img * a.wstride + tile] = 0;
+    }
+    return;
+  }
+  const int col = c0 + wave;                         // u cell 0..H-1
+  const bool active = col < ncols;
+  float2* hbuf = lds + wave * C_::STRIDE;
+  const double s = cells_per_metre(a.freq[ch], a.ndx);
+  const float2* tw = stage_twiddles<N>(ltw);
+
+  ColSpan span{0, 0, 0, 0};
+  if (active) {
+    const int* bnd = a.bnd + (size_t)img * (N + 2);
+    span = ColSpan{bnd[col + H], bnd[col + 1 + H], bnd[-col + H], bnd[-col + 1 + H]};
+  }
+  HalfIn<N> in;
+  int kd = 0, kc = 0;
+  if (a.sd != nullptr) grid_col_half<N, true>(a, span, hbuf, in, t, ch, s, lane, kd, kc);
+  else grid_col_half<N, false>(a, span, hbuf, in, t, ch, s, lane, kd, kc);
+  // baselines counted once: the direct entry of every cell column, plus the
+  // conjugate entries of columns whose mirror the image path never visits
+  const int kept_b = kd + (col > 0 ? kc : 0);
+  const int wcontrib = (col > 0 ? 2 : 1) * (kd + kc);
+  if (lane == 0) { red[wave] = wcontrib; red[CPW + wave] = kept_b; }
+  __syncthreads();                                   // also publishes the LDS twiddles
+  if (threadIdx.x == 0) {
+    int ws = 0, ks = 0;
+    for (int i = 0; i < CPW; ++i) {
+      ws += red[i];
+      ks += red[CPW + i];
+    }
+    a.wpart[(size_t)img * a.wstride + tile] = ws;
+    a.kpart[(size_t)img * a.wstride + tile] = ks;
+  }
+  if (active) {
+    // rows of the cutout straight from the last stage: output row m holds
+    // v-frequency q = (m - M/2) mod N
+    float2* dst = a.half + ((size_t)li * H + col) * a.M;
+    const int hm = a.M / 2;
+    wave_fft_half_emit<N, +1>(hbuf, lane, tw, in, [&](auto qb, float2 v) {
+      cutout_block<N, decltype(qb)::value>(lane, hm, [&](unsigned m) { store_at(dst, m, v); });
+    });
+  }
+}
+
 __global__ void k_grid_finish(ImgArgs a, int n_img) {
   const int img = blockIdx.x * blockDim.x + threadIdx.x;
   if (img >= n_img) return;

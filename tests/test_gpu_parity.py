@@ -251,6 +251,46 @@ def test_ties_edges_and_out_of_grid(weighting):
     assert rel_l2(img[0], r["image"]) <= REL_L2_FP32
 
 
+@pytest.mark.parametrize("n,nb", [(32, 60), (64, 300), (256, 900), (2048, 3000)])
+def test_half_length_exchange_sizes(n, nb):
+    """Natural weighting at power-of-two sizes takes the column kernel whose
+    stage exchanges pass through half-length LDS buffers; from 32 (two
+    butterflies in its first stage) to 2048, with ties and edges mixed in."""
+    print(f"\n[gpu] half-length column exchange N={n} B={nb}", flush=True)
+    rng = np.random.default_rng(n + nb)
+    uv = rng.uniform(-n / 2 - 2, n / 2 + 2, size=(nb, 2))
+    uv[:20] = np.round(uv[:20]) + 0.5                      # ties
+    uv[20:24, 0] = [n / 2 - 0.5, -n / 2 + 0.49, 0.0, 0.4]  # edge and origin columns
+    w, vis = _tiny(n=n, nb=nb, uv=uv, seed=n)
+    img, wsum, cnt, drop = _run_tiny(w, vis, 0)
+    r = oracle.image_one(vis[0, 0], uv[:, 0], uv[:, 1], w.freq_hz[0], n, w.pixscale, n, 0, 1)
+    assert np.array_equal(cnt[0], r["counts"])
+    assert drop[0] == nb - r["keep"].sum()
+    assert wsum[0] == r["W"]
+    e = rel_l2(img[0], r["image"])
+    print(f"  rel-L2 {e:.2e}", flush=True)
+    assert e <= REL_L2_FP32
+
+
+def test_columns_longer_than_one_gather_step():
+    """Columns of more than 4 x 64 sorted entries (direct plus mirror) load
+    their entries again for the upper half of the column; every tile width
+    gives the same bits."""
+    rng = np.random.default_rng(21)
+    n, nb = 64, 3000
+    uv = np.stack([rng.uniform(-3.4, 3.4, nb), rng.uniform(-30, 30, nb)], -1)
+    w, vis = _tiny(n=n, nb=nb, uv=uv, seed=21)
+    r = oracle.image_one(vis[0, 0], uv[:, 0], uv[:, 1], w.freq_hz[0], n, w.pixscale, n, 0, 1)
+    assert r["counts"][:, 0].sum() > 4 * 64                 # column 0 alone needs several steps
+    dev = device()
+    d = dict(vis=torch.from_numpy(vis).to(dev), uvw_m=torch.from_numpy(w.uvw_m).to(dev),
+             freq_hz=torch.from_numpy(w.freq_hz).to(dev))
+    w.weighting = 0
+    outs = [run_image(w, d, cols_per_wg=c)[0] for c in (2, 4, 8)]
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    assert rel_l2(outs[0].cpu().numpy()[0], r["image"]) <= REL_L2_FP32
+
+
 def test_all_flagged_and_non_finite_coordinates():
     n = 16
     w, vis = _tiny(n=n, nb=30, seed=4)
