@@ -355,15 +355,31 @@ constexpr size_t LDS_PER_CU = size_t(160) << 10;
 // Measured on MI355X: faster at N = 1024, slower than per-lane stores at
 // N = 2048 (4.85 against 4.1 ms per 384 images), so larger N keep those.
 constexpr int ROWS_BLOCK_STORE_MAX_N = 1024;
+// Row pass through half-length LDS buffers at power-of-two sizes up to 2048.
+template <int N>
+constexpr bool rows_half() { return plan_even(N) && N <= 2048; }
+template <int N>
+constexpr size_t rows_lds_base() { return rows_half<N>() ? RowsHalf<N>::LDS : Rows<N>::LDS; }
+
 template <int N, bool KB>
 void launch_rows(const blink_problem* p, ImgArgs& a, long long nwg, size_t lds, hipStream_t st) {
-  if constexpr (blocks_aligned(N) && N <= ROWS_BLOCK_STORE_MAX_N) {
-    if ((p->out_n / 2) % WAVE == 0) {
-      hipLaunchKernelGGL((k_rows<N, true, KB>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), lds, st, a);
-      return;
+  if constexpr (rows_half<N>()) {
+    if constexpr (blocks_aligned(N) && N <= ROWS_BLOCK_STORE_MAX_N) {
+      if ((p->out_n / 2) % WAVE == 0) {
+        hipLaunchKernelGGL((k_rows_half<N, true, KB>), dim3((unsigned)nwg), dim3(RowsHalf<N>::THREADS), lds, st, a);
+        return;
+      }
     }
+    hipLaunchKernelGGL((k_rows_half<N, false, KB>), dim3((unsigned)nwg), dim3(RowsHalf<N>::THREADS), lds, st, a);
+  } else {
+    if constexpr (blocks_aligned(N) && N <= ROWS_BLOCK_STORE_MAX_N) {
+      if ((p->out_n / 2) % WAVE == 0) {
+        hipLaunchKernelGGL((k_rows<N, true, KB>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), lds, st, a);
+        return;
+      }
+    }
+    hipLaunchKernelGGL((k_rows<N, false, KB>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), lds, st, a);
   }
-  hipLaunchKernelGGL((k_rows<N, false, KB>), dim3((unsigned)nwg), dim3(Rows<N>::THREADS), lds, st, a);
 }
 
 template <int N>
@@ -375,7 +391,7 @@ blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t s
   // kernel gridding runs at the default tile width only
   const int cpw = kb ? cols_per_wg(N) : (p->cols_per_wg ? p->cols_per_wg : cols_per_wg(N));
   if (cols_lds<N>(cpw, uni, kb) > LDS_PER_CU) return BLINK_E_UNSUPPORTED;
-  const size_t rows_lds = Rows<N>::LDS + (kb ? (size_t)p->out_n * sizeof(float) : 0);
+  const size_t rows_lds = rows_lds_base<N>() + (kb ? (size_t)p->out_n * sizeof(float) : 0);
   if (rows_lds > LDS_PER_CU) return BLINK_E_UNSUPPORTED;
   a.wtiles = (int)cdiv(N / 2, cpw);
   T_.begin(1);

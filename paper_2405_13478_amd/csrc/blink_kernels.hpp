@@ -1023,6 +1023,119 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
   }
 }
 
+// Row pass with the transforms' exchanges through half-length LDS buffers
+// (see wave_fft_half_emit): the same packing, shift, 1/W, cutout and stores
+// as k_rows, and the same tiling (one workgroup per row tile, or a
+// persistent grid walking the tiles). The workgroup fills the lower halves
+// of its PPW packed rows (z[k], k < N/2) from one load of the half-spectrum
+// slice, each wavefront takes its first stage's lower inputs, then the upper
+// halves (z[N - k]) follow from the same registers. With no prefetch across
+// tiles and half the LDS, three workgroups share a CU instead of two.
+template <int N>
+struct RowsHalf {
+  static constexpr int STRIDE = padded_len(N / 2) + ((4 - padded_len(N / 2) % 32) + 32) % 32;
+  static constexpr int PPW = Rows<N>::PPW;
+  static constexpr int THREADS = PPW * WAVE;
+  static constexpr int TW = TwLds<N>::ON ? tw_entries(N) : 0;
+  static constexpr size_t LDS = (size_t)(PPW * STRIDE + TW) * sizeof(float2);
+};
+
+template <int N, bool AL, bool KB>
+__global__ void __launch_bounds__(RowsHalf<N>::THREADS) k_rows_half(ImgArgs a) {
+  static_assert(!AL || blocks_aligned(N), "aligned cutout needs aligned blocks");
+  extern __shared__ float4 lds_raw[];
+  constexpr int H = N / 2;
+  constexpr int PPW = RowsHalf<N>::PPW;
+  constexpr int ST = RowsHalf<N>::STRIDE;
+  constexpr int THR = RowsHalf<N>::THREADS;
+  constexpr int EPT = (H * PPW + THR - 1) / THR;     // half-spectrum float4 loads per thread
+  constexpr int R0 = HalfIn<N>::R;
+  float2* lds = reinterpret_cast<float2*>(lds_raw);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), lane = threadIdx.x % WAVE;
+  const int M = a.M;
+  const int npair = M / 2;
+  const int ntr = (npair + PPW - 1) / PPW;           // row tiles per image
+  const int total = a.nimg * ntr;
+  const float2* tw = stage_twiddles<N>(lds + PPW * ST);
+  float* lcorr = reinterpret_cast<float*>(lds + PPW * ST + RowsHalf<N>::TW);
+  if (KB)
+    for (int l = threadIdx.x; l < a.M; l += THR) lcorr[l] = 1.0f / kb_taper((float)(l - a.M / 2) / N, a);
+
+#pragma nounroll
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    // lane-dependent addresses are formed inside the loop: hoisted out of it
+    // they would stay live across the transforms and cost occupancy
+    int lane_i = lane, ln = threadIdx.x;
+    asm volatile("" : "+v"(lane_i), "+v"(ln));
+    // thread t serves pair slot t % PPW and columns t / PPW + i * (THR / PPW)
+    const int kt = ln / PPW, pt = ln % PPW;
+    const int li = tile / ntr, p0 = (tile % ntr) * PPW;
+    const int img = a.img0 + li;
+    const int nz = min(H, a.ncz[img]);
+    float4 ab[EPT];
+    {
+      const float4* src = reinterpret_cast<const float4*>(a.half + (size_t)li * H * M) + (p0 + pt);
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int k = kt + i * (THR / PPW);
+        ab[i] = (k < nz && p0 + pt < npair) ? src[(size_t)k * (M / 2)] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+    const float W = KB ? sum_partials_f(a.wpart, img, a.wstride, a.wtiles, lane_i)
+                       : (float)sum_partials(a.wpart, img, a.wstride, a.wtiles, lane_i);
+    const float scale = a.norm ? (W > 0 ? 1.0f / W : 0.0f) : 1.0f;
+    if (p0 == 0 && ln == 0 && a.weight_sum) a.weight_sum[img] = W;
+    float2* zs = lds + pt * ST;                       // the packed row this thread fills
+    float2* z = lds + wave * ST;                      // the packed row this wavefront transforms
+    HalfIn<N> in;
+    __syncthreads();                                  // previous tile's rows have left LDS
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {                   // lower half: z[k] = A[k] + i B[k]
+      const int k = kt + i * (THR / PPW);
+      if (k < H) {
+        const float4 v = ab[i];
+        zs[pad(k)] = k == 0 ? make_float2(v.x, v.z) : make_float2(v.x - v.w, v.y + v.z);
+      }
+    }
+    __syncthreads();
+    half_read<N, R0, 0>(z, lane_i, in.v);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {                   // upper half: z[N - k] = conj A[k] + i conj B[k]
+      const int k = kt + i * (THR / PPW);
+      if (k < H) {
+        const float4 v = ab[i];
+        zs[pad(k == 0 ? 0 : H - k)] = k == 0 ? make_float2(0.f, 0.f) : make_float2(v.x + v.w, v.z - v.y);
+      }
+    }
+    __syncthreads();
+    half_read<N, R0, 1>(z, lane_i, in.v);
+    const int pair = p0 + wave;
+    if (pair < npair) {
+      float* r0 = a.images + ((size_t)img * M + 2 * pair) * M;
+      float* r1 = r0 + M;
+      float s0 = scale, s1 = scale;
+      if (KB) {
+        s0 *= lcorr[2 * pair];
+        s1 *= lcorr[2 * pair + 1];
+      }
+      int hm = M / 2;
+      asm volatile("" : "+s"(hm));   // block tests stay inside the loop (hoisted they spill)
+      // image columns of the cutout straight from the last stage: column l
+      // holds u-frequency q = (l - M/2) mod N; row 2p is Re z, row 2p+1 is Im z
+      wave_fft_half_emit<N, +1>(z, lane_i, tw, in, [&](auto qb, float2 v) {
+        auto st = [&](unsigned l) {
+          const float cl = KB ? lcorr[l] : 1.0f;
+          store_at(r0, l, v.x * s0 * cl);
+          store_at(r1, l, v.y * s1 * cl);
+        };
+        if constexpr (AL) cutout_block_aligned<N, decltype(qb)::value>(lane_i, hm, st);
+        else cutout_lane<N, decltype(qb)::value>(lane_i, hm, st);
+      });
+    }
+  }
+}
+
 // ============================================================== dynamic spectra
 // Transpose of the image cube [T][C][P] to per-pixel time series [P][C][T]
 // with the reference image subtracted on the way. One workgroup per tile of
