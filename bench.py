@@ -134,7 +134,7 @@ EXTRA_STATS = {
 def extra_stats_cmd(k):
     d, flags, _, _ = EXTRA_STATS[k]
     return f"rocprofv3 --kernel-trace --stats --output-format csv -d OUT/{d} -o bench -- python3 bench.py {flags}"
-KERNEL_KEYS = {"grid_cols": "k_grid_cols<1024, 0", "rows": "k_rows<1024"}
+KERNEL_KEYS = {"grid_cols": "k_grid_cols_half<1024", "rows": "k_rows_half<1024"}
 
 
 def _csv(path):
