@@ -310,28 +310,27 @@ void launch_cols_image(ImgArgs& a, int n, hipStream_t st) {
   hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, UNI, CPW>), g1, dim3(C_::THREADS), C_::lds_bytes(UNI), st, a);
 }
 
-template <int N, int CPW>
+template <int N, int CPW, bool UNI>
 void launch_cols_half(ImgArgs& a, int n, hipStream_t st) {
-  using C_ = ColsHalf<N, CPW>;
+  using C_ = ColsHalf<N, CPW, UNI>;
   a.wtiles = a.ntiles = (int)cdiv(N / 2, CPW);
   const dim3 g1((unsigned)(cdiv(n, 8) * 8LL * a.ntiles));
-  hipLaunchKernelGGL((k_grid_cols_half<N, CPW>), g1, dim3(C_::THREADS), C_::LDS, st, a);
+  hipLaunchKernelGGL((k_grid_cols_half<N, CPW, UNI>), g1, dim3(C_::THREADS), C_::LDS, st, a);
 }
 
-// Natural weighting at power-of-two sizes up to 2048 takes the column kernel
-// whose exchanges go through half-length LDS buffers (measured at N = 1024:
-// 4.52 ms per 7,680 images against 5.20 ms with full-length buffers); uniform
-// weighting (per-cell counts), other sizes and kernel gridding take the
-// full-length one.
+// Power-of-two sizes up to 2048 take the column kernel whose exchanges go
+// through half-length LDS buffers (measured at N = 1024, natural weighting:
+// 4.52 ms per 7,680 images against 5.20 ms with full-length buffers); other
+// sizes and kernel gridding take the full-length one.
 template <int N>
-constexpr bool cols_half(bool uni) { return plan_even(N) && N <= 2048 && !uni; }
+constexpr bool cols_half() { return plan_even(N) && N <= 2048; }
 
 template <int N, bool UNI>
 void launch_cols_image(ImgArgs& a, int n, int cpw, hipStream_t st) {
-  if constexpr (cols_half<N>(UNI)) {
-    if (cpw == 2) launch_cols_half<N, 2>(a, n, st);
-    else if (cpw == 4) launch_cols_half<N, 4>(a, n, st);
-    else launch_cols_half<N, 8>(a, n, st);
+  if constexpr (cols_half<N>()) {
+    if (cpw == 2) launch_cols_half<N, 2, UNI>(a, n, st);
+    else if (cpw == 4) launch_cols_half<N, 4, UNI>(a, n, st);
+    else launch_cols_half<N, 8, UNI>(a, n, st);
   } else {
     if (cpw == 2) launch_cols_image<N, UNI, 2>(a, n, st);
     else if (cpw == 4) launch_cols_image<N, UNI, 4>(a, n, st);
@@ -343,8 +342,12 @@ void launch_cols_image(ImgArgs& a, int n, int cpw, hipStream_t st) {
 // against the 160 KiB of a gfx950 CU before any launch).
 template <int N>
 size_t cols_lds(int cpw, bool uni, bool kb) {
-  if (cols_half<N>(uni) && !kb)
-    return cpw == 2 ? ColsHalf<N, 2>::LDS : cpw == 4 ? ColsHalf<N, 4>::LDS : ColsHalf<N, 8>::LDS;
+  if (cols_half<N>() && !kb) {
+    if (uni) return cpw == 2 ? ColsHalf<N, 2, true>::LDS : cpw == 4 ? ColsHalf<N, 4, true>::LDS
+                                                            : ColsHalf<N, 8, true>::LDS;
+    return cpw == 2 ? ColsHalf<N, 2, false>::LDS : cpw == 4 ? ColsHalf<N, 4, false>::LDS
+                                                            : ColsHalf<N, 8, false>::LDS;
+  }
   return cpw == 2 ? Cols<N, 2>::lds_bytes(uni) : cpw == 4 ? Cols<N, 4>::lds_bytes(uni)
                                                           : Cols<N, 8>::lds_bytes(uni);
 }

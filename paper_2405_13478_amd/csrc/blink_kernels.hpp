@@ -719,30 +719,34 @@ __global__ void __launch_bounds__((Cols<N, CPW>::THREADS)) k_grid_cols(ImgArgs a
 }
 
 // ------------------------------------------- column pass, half-length LDS
-// The image-mode column kernel (natural weighting, nearest cell) with every
-// LDS exchange of the column through N/2 points: the rows below N/2 are
-// gridded and handed to the first stage's registers, then the rows above,
-// and the stages exchange in two rounds (wave_fft_half_emit). Each row
-// receives the same adds in the same order as in the full-buffer kernel.
-template <int N, int CPW>
+// The image-mode column kernel (nearest cell) with every LDS exchange of the
+// column through N/2 points: the rows below N/2 are gridded (and, with
+// uniform weighting, divided by their counts) and handed to the first
+// stage's registers, then the rows above, and the stages exchange in two
+// rounds (wave_fft_half_emit). Each row receives the same adds in the same
+// order as in the full-buffer kernel.
+template <int N, int CPW, bool UNI>
 struct ColsHalf {
   static constexpr int STRIDE = padded_len(N / 2);
   static constexpr int THREADS = CPW * WAVE;
   static constexpr int TW = TwLds<N>::ON ? tw_entries(N) : 0;
-  static constexpr size_t LDS = (size_t)(CPW * STRIDE + TW) * sizeof(float2);
+  static constexpr size_t LDS = (size_t)(CPW * STRIDE + TW) * sizeof(float2) +
+                                (UNI ? (size_t)CPW * (N / 2) * sizeof(int) : 0);
 };
 
-// LDS adds of the kept entries of a step whose row lies in half HF
-template <int N, int HF>
-__device__ __forceinline__ void step_add_half(const EntryStep& e, float2* hbuf) {
+// LDS adds (and counts) of the kept entries of a step whose row lies in half HF
+template <int N, int HF, bool COUNT>
+__device__ __forceinline__ void step_add_half(const EntryStep& e, float2* hbuf, int* hcnt) {
 #pragma unroll
   for (int u = 0; u < GU; ++u) {
     if (e.ok[u] && (e.row[u] >= N / 2) == (HF == 1)) {
       float2 v = e.val[u];
       if (e.cj[u]) v.y = -v.y;
-      float2* p = &hbuf[pad(e.row[u] - HF * (N / 2))];
+      const int r = e.row[u] - HF * (N / 2);
+      float2* p = &hbuf[pad(r)];
       atomicAdd(&p->x, v.x);
       atomicAdd(&p->y, v.y);
+      if (COUNT) atomicAdd(&hcnt[r], 1);
     }
   }
 }
@@ -755,28 +759,50 @@ __device__ __forceinline__ void step_count(const EntryStep& e, int& kd, int& kc)
   }
 }
 
-template <int N>
-__device__ __forceinline__ void zero_half(float2* hbuf, int lane) {
+template <int N, bool UNI>
+__device__ __forceinline__ void zero_half(float2* hbuf, int* hcnt, int lane) {
   for (int r = lane; r < padded_len(N / 2); r += WAVE) hbuf[r] = make_float2(0.f, 0.f);
+  if (UNI)
+    for (int r = lane; r < N / 2; r += WAVE) hcnt[r] = 0;
+}
+
+// Uniform weighting of one half: every occupied cell divided by its count;
+// returns this lane's number of occupied cells.
+template <int N>
+__device__ __forceinline__ int uniform_half(float2* hbuf, const int* hcnt, int lane) {
+  int occ = 0;
+  for (int r = lane; r < N / 2; r += WAVE) {
+    const int n = hcnt[r];
+    if (n > 0) {
+      float2 v = hbuf[pad(r)];
+      v.x = v.x / (float)n;
+      v.y = v.y / (float)n;
+      hbuf[pad(r)] = v;
+      ++occ;
+    }
+  }
+  return occ;
 }
 
 // Grids one column in two halves and loads the first stage's inputs. A
 // column of at most GU x 64 entries (the usual case) keeps its one step of
 // entries in registers for both halves; longer columns load them again.
-template <int N, bool ROT>
-__device__ __forceinline__ void grid_col_half(const ImgArgs& a, const ColSpan& c, float2* hbuf, HalfIn<N>& in,
-                                              int t, int ch, double s, int lane, int& kd, int& kc) {
+// occ: this lane's occupied cells (uniform weighting).
+template <int N, bool ROT, bool UNI>
+__device__ __forceinline__ void grid_col_half(const ImgArgs& a, const ColSpan& c, float2* hbuf, int* hcnt,
+                                              HalfIn<N>& in, int t, int ch, double s, int lane, int& kd,
+                                              int& kc, int& occ) {
   constexpr int R0 = HalfIn<N>::R;
   const int total = c.total();
   const bool one = total <= GU * WAVE;
   EntryStep e;
-  zero_half<N>(hbuf, lane);
+  zero_half<N, UNI>(hbuf, hcnt, lane);
   wave_sync();
   if (one) {
     if (total > 0) {
       step_keys<ROT>(a, c, 0, t, lane, e);
       step_gather<N, ROT>(a, t, ch, s, e);
-      step_add_half<N, 0>(e, hbuf);
+      step_add_half<N, 0, UNI>(e, hbuf, hcnt);
       step_count(e, kd, kc);
     }
   } else {
@@ -784,36 +810,44 @@ __device__ __forceinline__ void grid_col_half(const ImgArgs& a, const ColSpan& c
       EntryStep f;
       step_keys<ROT>(a, c, i0, t, lane, f);
       step_gather<N, ROT>(a, t, ch, s, f);
-      step_add_half<N, 0>(f, hbuf);
+      step_add_half<N, 0, UNI>(f, hbuf, hcnt);
       step_count(f, kd, kc);
     }
   }
   wave_sync();
+  if (UNI) {
+    occ += uniform_half<N>(hbuf, hcnt, lane);
+    wave_sync();
+  }
   half_read<N, R0, 0>(hbuf, lane, in.v);
   wave_sync();
-  zero_half<N>(hbuf, lane);
+  zero_half<N, UNI>(hbuf, hcnt, lane);
   wave_sync();
   if (one) {
-    if (total > 0) step_add_half<N, 1>(e, hbuf);
+    if (total > 0) step_add_half<N, 1, UNI>(e, hbuf, hcnt);
   } else {
     for (int i0 = 0; i0 < total; i0 += GU * WAVE) {
       EntryStep f;
       step_keys<ROT>(a, c, i0, t, lane, f);
       step_gather<N, ROT>(a, t, ch, s, f);
-      step_add_half<N, 1>(f, hbuf);
+      step_add_half<N, 1, UNI>(f, hbuf, hcnt);
     }
   }
   wave_sync();
+  if (UNI) {
+    occ += uniform_half<N>(hbuf, hcnt, lane);
+    wave_sync();
+  }
   half_read<N, R0, 1>(hbuf, lane, in.v);
   wave_sync();
 }
 
-// Same tiling, XCD mapping and outputs as k_grid_cols<N, MODE_IMAGE, false, CPW>.
-template <int N, int CPW>
-__global__ void __launch_bounds__((ColsHalf<N, CPW>::THREADS)) k_grid_cols_half(ImgArgs a) {
+// Same tiling, XCD mapping and outputs as k_grid_cols<N, MODE_IMAGE, UNI, CPW>.
+template <int N, int CPW, bool UNI>
+__global__ void __launch_bounds__((ColsHalf<N, CPW, UNI>::THREADS)) k_grid_cols_half(ImgArgs a) {
   extern __shared__ float4 lds_raw[];
   __shared__ int red[2 * CPW];
-  using C_ = ColsHalf<N, CPW>;
+  using C_ = ColsHalf<N, CPW, UNI>;
   constexpr int H = N / 2;
   const int L = blockIdx.x;
   const int r8 = L >> 3;
@@ -822,6 +856,7 @@ __global__ void __launch_bounds__((ColsHalf<N, CPW>::THREADS)) k_grid_cols_half(
   if (li >= a.nimg) return;                          // padding of the last group of 8 images
   float2* lds = reinterpret_cast<float2*>(lds_raw);
   float2* ltw = lds + CPW * C_::STRIDE;
+  int* lcnt = reinterpret_cast<int*>(ltw + C_::TW);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), lane = threadIdx.x % WAVE;
   const int img = a.img0 + li;
   const int t = img / a.C, ch = img - t * a.C;
@@ -837,6 +872,7 @@ __global__ void __launch_bounds__((ColsHalf<N, CPW>::THREADS)) k_grid_cols_half(
   const int col = c0 + wave;                         // u cell 0..H-1
   const bool active = col < ncols;
   float2* hbuf = lds + wave * C_::STRIDE;
+  int* hcnt = UNI ? lcnt + wave * H : nullptr;
   const double s = cells_per_metre(a.freq[ch], a.ndx);
   const float2* tw = stage_twiddles<N>(ltw);
 
@@ -846,13 +882,20 @@ __global__ void __launch_bounds__((ColsHalf<N, CPW>::THREADS)) k_grid_cols_half(
     span = ColSpan{bnd[col + H], bnd[col + 1 + H], bnd[-col + H], bnd[-col + 1 + H]};
   }
   HalfIn<N> in;
-  int kd = 0, kc = 0;
-  if (a.sd != nullptr) grid_col_half<N, true>(a, span, hbuf, in, t, ch, s, lane, kd, kc);
-  else grid_col_half<N, false>(a, span, hbuf, in, t, ch, s, lane, kd, kc);
+  int kd = 0, kc = 0, occ = 0;
+  if (a.sd != nullptr) grid_col_half<N, true, UNI>(a, span, hbuf, hcnt, in, t, ch, s, lane, kd, kc, occ);
+  else grid_col_half<N, false, UNI>(a, span, hbuf, hcnt, in, t, ch, s, lane, kd, kc, occ);
   // baselines counted once: the direct entry of every cell column, plus the
   // conjugate entries of columns whose mirror the image path never visits
   const int kept_b = kd + (col > 0 ? kc : 0);
-  const int wcontrib = (col > 0 ? 2 : 1) * (kd + kc);
+  const int mult = col > 0 ? 2 : 1;
+  int wcontrib;
+  if (UNI) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) occ += __shfl_xor(occ, o);
+    wcontrib = mult * occ;
+  } else {
+    wcontrib = mult * (kd + kc);
+  }
   if (lane == 0) { red[wave] = wcontrib; red[CPW + wave] = kept_b; }
   __syncthreads();                                   // also publishes the LDS twiddles
   if (threadIdx.x == 0) {

@@ -251,19 +251,21 @@ def test_ties_edges_and_out_of_grid(weighting):
     assert rel_l2(img[0], r["image"]) <= REL_L2_FP32
 
 
+@pytest.mark.parametrize("weighting", [0, 1])
 @pytest.mark.parametrize("n,nb", [(32, 60), (64, 300), (256, 900), (2048, 3000)])
-def test_half_length_exchange_sizes(n, nb):
-    """Natural weighting at power-of-two sizes takes the column kernel whose
-    stage exchanges pass through half-length LDS buffers; from 32 (two
-    butterflies in its first stage) to 2048, with ties and edges mixed in."""
-    print(f"\n[gpu] half-length column exchange N={n} B={nb}", flush=True)
+def test_half_length_exchange_sizes(n, nb, weighting):
+    """Power-of-two sizes take the column kernel whose stage exchanges pass
+    through half-length LDS buffers (with uniform weighting, the cells of each
+    half are divided by their counts before the half is handed on); from 32
+    (two butterflies in its first stage) to 2048, with ties and edges mixed in."""
+    print(f"\n[gpu] half-length column exchange N={n} B={nb} weighting={weighting}", flush=True)
     rng = np.random.default_rng(n + nb)
     uv = rng.uniform(-n / 2 - 2, n / 2 + 2, size=(nb, 2))
     uv[:20] = np.round(uv[:20]) + 0.5                      # ties
     uv[20:24, 0] = [n / 2 - 0.5, -n / 2 + 0.49, 0.0, 0.4]  # edge and origin columns
     w, vis = _tiny(n=n, nb=nb, uv=uv, seed=n)
-    img, wsum, cnt, drop = _run_tiny(w, vis, 0)
-    r = oracle.image_one(vis[0, 0], uv[:, 0], uv[:, 1], w.freq_hz[0], n, w.pixscale, n, 0, 1)
+    img, wsum, cnt, drop = _run_tiny(w, vis, weighting)
+    r = oracle.image_one(vis[0, 0], uv[:, 0], uv[:, 1], w.freq_hz[0], n, w.pixscale, n, weighting, 1)
     assert np.array_equal(cnt[0], r["counts"])
     assert drop[0] == nb - r["keep"].sum()
     assert wsum[0] == r["W"]
