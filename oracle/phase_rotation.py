@@ -18,6 +18,16 @@ rotates them to the pointing centre before imaging. Readings used here:
   plane, shifted so that the new centre is at its middle;
 * the factor multiplies V' after the gains (both are per-visibility
   scalars, so their order does not matter).
+
+Sec. 4.2 (i), the cable correction, reads as follows here: antenna a's
+signal path is longer by an electrical length l_a (metres of free-space
+propagation), which delays its voltage by l_a / c and multiplies its
+component at frequency nu by exp(-2 pi i nu l_a / c); the visibility of
+baseline (ant1, ant2) = x_ant1 conj(x_ant2) then carries
+exp(-2 pi i nu (l_ant1 - l_ant2) / c), and the correction multiplies it by
+exp(+2 pi i nu (l_ant1 - l_ant2) / c). It is the same factor as the
+geometric rotation with the path difference l_ant1 - l_ant2, so the two add
+into one delay per baseline.
 """
 from __future__ import annotations
 
@@ -33,21 +43,31 @@ def geometric_delay(uvw_m, l0: float, m0: float):
     return uvw[..., 0] * l0 + uvw[..., 1] * m0 + uvw[..., 2] * (n0 - 1.0)
 
 
-def rotate(vis, uvw_m, freq_hz: float, l0: float, m0: float):
-    """V exp(+2 pi i d nu / c) for one channel (vis and uvw over the same baselines)."""
+def cable_delay(cable_m, ant1, ant2):
+    """l_ant1 - l_ant2 in metres per baseline."""
+    cab = np.asarray(cable_m, dtype=np.float64)
+    return cab[np.asarray(ant1)] - cab[np.asarray(ant2)]
+
+
+def rotate(vis, uvw_m, freq_hz: float, l0: float, m0: float, cable_m=None, ant1=None, ant2=None):
+    """V exp(+2 pi i d nu / c) for one channel (vis and uvw over the same baselines),
+    d the geometric delay plus, with cable lengths, l_ant1 - l_ant2."""
     d = geometric_delay(uvw_m, l0, m0)
+    if cable_m is not None:
+        d = d + cable_delay(cable_m, ant1, ant2)
     return np.asarray(vis, dtype=np.complex128) * np.exp(2j * np.pi * d * (np.float64(freq_hz) / C_LIGHT))
 
 
 def image_batch_rotated(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, weighting, norm, l0, m0,
-                        flags=None, gains=None, ant1=None, ant2=None, images=None):
-    """Images [len][M][M] and W [len] with the phase centre rotated to (l0, m0)."""
+                        flags=None, gains=None, ant1=None, ant2=None, images=None, cable_m=None):
+    """Images [len][M][M] and W [len] with the phase centre rotated to (l0, m0)
+    and, with cable lengths, the cable correction applied."""
     T, C, B = vis.shape
     idx = range(T * C) if images is None else list(images)
     out, ws = [], []
     for i in idx:
         t, c = divmod(int(i), C)
-        v = rotate(vis[t, c], uvw_m[t], freq_hz[c], l0, m0)
+        v = rotate(vis[t, c], uvw_m[t], freq_hz[c], l0, m0, cable_m, ant1, ant2)
         r = image_one(v, uvw_m[t, :, 0], uvw_m[t, :, 1], freq_hz[c], grid_n, pixscale, out_n, weighting,
                       norm, None if flags is None else flags[t], gains, ant1, ant2)
         out.append(r["image"])

@@ -6,7 +6,11 @@
 * for a coplanar array (w = 0) a source at (l1, m1) moves to the pixel of
   (l1 - l0, m1 - m0) (point-source placement of the imaging oracle);
 * the delay is the dot product of the baseline with s0 - z (a brute-force
-  check of the n0 - 1 term).
+  check of the n0 - 1 term);
+* cable correction: equal lengths change nothing; visibilities correlated
+  from cable-delayed voltages of a zenith source become constant and image
+  at the centre with its flux; lengths that mimic a plane wave from (l0, m0)
+  give exactly the geometric rotation to (l0, m0) on a coplanar array.
 """
 import numpy as np
 
@@ -66,3 +70,57 @@ def test_delay_is_baseline_dot_direction_change():
     for b in range(0, len(uvw), 37):
         ref = sum(uvw[b, k] * (s0[k] - z[k]) for k in range(3))
         assert abs(pr.geometric_delay(uvw[b], l0, m0) - ref) <= 1e-12
+
+
+# ------------------------------------------------------------ cable correction
+def _antennas(seed, na=24, span=15.0):
+    rng = np.random.default_rng(seed)
+    xy = rng.uniform(-span, span, size=(na, 2))
+    a1, a2 = np.triu_indices(na, k=1)
+    uvw = np.zeros((len(a1), 3))
+    uvw[:, :2] = xy[a2] - xy[a1]                   # baseline (ant1, ant2): position of ant2 - ant1
+    return xy, a1.astype(np.int32), a2.astype(np.int32), uvw
+
+
+def test_equal_cable_lengths_change_nothing():
+    xy, a1, a2, uvw = _antennas(5)
+    v = np.exp(1j * np.linspace(0, 2, len(a1)))
+    cab = np.full(len(xy), 123.25)
+    assert np.array_equal(pr.rotate(v, uvw, 1.6e8, 0.0, 0.0, cab, a1, a2), v.astype(np.complex128))
+
+
+def test_cable_delayed_voltages_are_corrected():
+    # a zenith plane wave seen through cables of different electrical length:
+    # antenna a's voltage is the common signal delayed by l_a / c. The
+    # correlated products x_i conj(x_j) differ from baseline to baseline until
+    # corrected; corrected, all equal |s|^2 and the image of the zenith source
+    # peaks at the centre with its flux.
+    xy, a1, a2, uvw = _antennas(6)
+    rng = np.random.default_rng(7)
+    cab = rng.uniform(0.0, 300.0, len(xy))
+    freq = 1.55e8
+    s = 2.0 * np.exp(0.4j)
+    x = s * np.exp(-2j * np.pi * freq * cab / oracle.C_LIGHT)
+    vis = x[a1] * np.conj(x[a2])
+    assert np.ptp(np.angle(vis)) > 1.0
+    r = pr.rotate(vis, uvw, freq, 0.0, 0.0, cab, a1, a2)
+    assert np.allclose(r, abs(s) ** 2, rtol=0, atol=1e-9)
+    n = 64
+    img = pr.image_batch_rotated(vis[None, None], uvw[None], np.array([freq]), n, 1.0 / (3 * 60.0), n, 0, 1,
+                                 0.0, 0.0, ant1=a1, ant2=a2, cable_m=cab)[0][0]
+    assert np.unravel_index(np.argmax(img), img.shape) == (n // 2, n // 2)
+    assert abs(img[n // 2, n // 2] - abs(s) ** 2) <= 1e-9
+
+
+def test_cable_lengths_of_a_tilted_plane_equal_the_geometric_rotation():
+    # electrical lengths l_a = -(x_a l0 + y_a m0) delay each antenna as a plane
+    # wave from (l0, m0) would; on a coplanar array the cable correction then
+    # equals the geometric rotation to (l0, m0), term by term
+    xy, a1, a2, uvw = _antennas(8)
+    l0, m0 = 0.17, -0.09
+    cab = -(xy[:, 0] * l0 + xy[:, 1] * m0)
+    v = np.exp(1j * np.linspace(0, 5, len(a1)))
+    freq = 1.9e8
+    by_cable = pr.rotate(v, uvw, freq, 0.0, 0.0, cab, a1, a2)
+    by_geometry = pr.rotate(v, uvw, freq, l0, m0)
+    assert np.allclose(by_cable, by_geometry, rtol=0, atol=1e-12)
