@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
 KB_SUPPORT = 6                 # Kaiser-Bessel support (cells) of the kernel-gridding workload
 ROT_LM = (0.05, 0.03)          # phase centre of the rotation workload (direction cosines)
+CABLE_MAX_M = 500.0            # rotation workload: electrical cable lengths uniform in [0, 500) m
 METRIC = "dirty images/s and visibilities/s at 128 tiles, 1024² grid; % HBM roofline"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_grid_cols_rows_widefield1024.json")
 CSRC = os.path.join(ROOT, "paper_2405_13478_amd", "csrc")
@@ -260,7 +261,7 @@ def _setup(args, synth):
 
 DESCRIPTION = {
     "widefield": "widefield 128 tiles (8128 baselines), 768 ch x 100 timesteps, 1024^2 grid -> 512^2 cutout, natural weighting",
-    "widefield_rot": "widefield 128 tiles (8128 baselines), 768 ch x 100 timesteps, 1024^2 grid -> 512^2 cutout, natural weighting, phase centre rotated to (l, m) = (0.05, 0.03) at load",
+    "widefield_rot": "widefield 128 tiles (8128 baselines), 768 ch x 100 timesteps, 1024^2 grid -> 512^2 cutout, natural weighting, phase centre rotated to (l, m) = (0.05, 0.03) and per-antenna cable lengths (uniform 0-500 m) corrected at load",
     "widefield_kb": "widefield 128 tiles (8128 baselines), 768 ch x 100 timesteps, 1024^2 grid -> 512^2 cutout, natural weighting, Kaiser-Bessel gridding kernel of 6 cells with taper correction",
     "plain": "plain single image, 32 antennas (496 baselines), 1 ch at 160 MHz, 128^2, natural weighting",
     "allsky": "station all-sky, 256 antennas (32640 baselines), 32 ch x 1000 timesteps (32,000 images), 180^2, uniform weighting, 2-10% flagged per timestep",
@@ -322,6 +323,11 @@ def bench_images(args, np, torch, blink, synth, dev):
     M, N, H, B = w.out_n, w.grid_n, w.grid_n // 2, w.n_bl
     ksup = KB_SUPPORT if args.workload == "widefield_kb" else 0
     plm = ROT_LM if args.workload == "widefield_rot" else (0.0, 0.0)
+    cable = ant1 = ant2 = None
+    if args.workload == "widefield_rot":
+        cable = torch.from_numpy(np.random.default_rng(2405).uniform(0.0, CABLE_MAX_M, w.n_ant)).to(dev)
+        ant1 = torch.from_numpy(w.ant1).to(dev)
+        ant2 = torch.from_numpy(w.ant2).to(dev)
     images = torch.empty((n_img, M, M), dtype=torch.float32, device=dev)   # reused per step
     ws_cache = {}
 
@@ -333,7 +339,7 @@ def bench_images(args, np, torch, blink, synth, dev):
                                      args.cols_per_wg, args.rows_wg)
         tunings[vbytes] = tun
         p = blink.blink.make_problem(v[:TT], uvw[:TT], freq, N, w.pixscale, M, w.weighting, w.norm,
-                                     None, **tun, kernel_support=ksup, phase_lm=plm)
+                                     None, **tun, kernel_support=ksup, phase_lm=plm, cable_m=cable)
         ws_cache[vbytes] = ws = blink.workspace(p, blink.CALL_IMAGE, dev)
 
         def run(k, tm):
@@ -342,7 +348,7 @@ def bench_images(args, np, torch, blink, synth, dev):
             blink.image_batch(v[sl], uvw[sl], freq, grid_n=N, pixscale=w.pixscale, out_n=M,
                               weighting=w.weighting, norm=w.norm, flags=None if flags is None else flags[sl],
                               vis_scale=scale, images=images, ws=ws, times=tm, **tun, kernel_support=ksup,
-                              phase_lm=plm)
+                              phase_lm=plm, ant1=ant1, ant2=ant2, cable_m=cable)
         return run
 
     ncz = np.concatenate([nonzero_columns(w, slice(b * TT, (b + 1) * TT))

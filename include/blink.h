@@ -74,6 +74,15 @@
  *   tangent plane, shifted by (l0, m0). The delay is formed in double at the
  *   sort, the phase in cycles in double, its sine and cosine in float.
  *   blink_degrid_adjoint with a rotation returns BLINK_E_UNSUPPORTED.
+ * - Cable correction (blink_inputs.cable_m != NULL; Sec. 4.2 (i)): antenna
+ *   a's signal path is longer by the electrical length l_a metres, which
+ *   multiplies its voltage by exp(-2 pi i nu l_a / c0); each V' of baseline
+ *   (ant1, ant2) is multiplied by exp(+2 pi i (l_ant1 - l_ant2) nu_c / c0).
+ *   The term adds to the geometric delay above (one factor per visibility).
+ *   It needs ant1, ant2 (indices < n_ant, not checked on the device) and
+ *   n_ant >= 1; blink_degrid_adjoint with cable lengths returns
+ *   BLINK_E_UNSUPPORTED. Per-antenna complex gains (Sec. 4.2 (ii)) are the
+ *   `gains` input.
  */
 #ifndef BLINK_H
 #define BLINK_H
@@ -143,6 +152,7 @@ typedef struct {          /* device pointers; the optional ones may be NULL     
   const int32_t*   ant1;      /* [B] antenna of the first input (required with gains)    */
   const int32_t*   ant2;      /* [B] antenna of the second input                         */
   const blink_c32* gains;     /* [A] per-antenna complex gains, or NULL                  */
+  const double*    cable_m;   /* [A] electrical cable length per antenna (m), or NULL    */
 } blink_inputs;
 
 /* Human-readable name of a status code (static string). */

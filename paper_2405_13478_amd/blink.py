@@ -53,7 +53,7 @@ class Problem(ctypes.Structure):
 class Inputs(ctypes.Structure):
     _fields_ = [("vis", ctypes.c_void_p), ("vis_scale", ctypes.c_void_p), ("uvw_m", ctypes.c_void_p),
                 ("freq_hz", ctypes.c_void_p), ("flags", ctypes.c_void_p), ("ant1", ctypes.c_void_p),
-                ("ant2", ctypes.c_void_p), ("gains", ctypes.c_void_p)]
+                ("ant2", ctypes.c_void_p), ("gains", ctypes.c_void_p), ("cable_m", ctypes.c_void_p)]
 
 
 class KernelTimes(ctypes.Structure):
@@ -141,7 +141,7 @@ def _check(code, what):
 
 def make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n=None, weighting=NATURAL,
                  norm=NORM_WEIGHTS, gains=None, chunk_images=0, cols_per_wg=0, rows_wg=0,
-                 kernel_support=0, kernel_beta=-1.0, phase_lm=(0.0, 0.0)) -> Problem:
+                 kernel_support=0, kernel_beta=-1.0, phase_lm=(0.0, 0.0), cable_m=None) -> Problem:
     if vis.dtype == torch.complex64:
         T, C, B = vis.shape
         vt = VIS_C64
@@ -152,7 +152,8 @@ def make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n=None, weighting=NA
         vt = VIS_F16 if vis.dtype == torch.float16 else VIS_BF16
     else:
         raise ValueError(f"unsupported visibility dtype {vis.dtype}")
-    return Problem(n_time=T, n_chan=C, n_bl=B, n_ant=0 if gains is None else gains.shape[0],
+    n_ant = gains.shape[0] if gains is not None else (cable_m.shape[0] if cable_m is not None else 0)
+    return Problem(n_time=T, n_chan=C, n_bl=B, n_ant=n_ant,
                    grid_n=grid_n, out_n=grid_n if out_n is None else out_n,
                    pixscale=float(pixscale), weighting=int(weighting), norm=int(norm),
                    vis_type=vt, chunk_images=int(chunk_images), cols_per_wg=int(cols_per_wg),
@@ -161,7 +162,7 @@ def make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n=None, weighting=NA
 
 
 def make_inputs(p: Problem, vis, uvw_m, freq_hz, flags=None, vis_scale=None, ant1=None,
-                ant2=None, gains=None):
+                ant2=None, gains=None, cable_m=None):
     T, C, B = p.n_time, p.n_chan, p.n_bl
     _dev(vis, "vis")
     _dev(uvw_m, "uvw_m", torch.float64, (T, B, 3))
@@ -171,9 +172,13 @@ def make_inputs(p: Problem, vis, uvw_m, freq_hz, flags=None, vis_scale=None, ant
     _dev(ant1, "ant1", torch.int32, (B,))
     _dev(ant2, "ant2", torch.int32, (B,))
     _dev(gains, "gains", torch.complex64)
-    keep = (vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains)
+    _dev(cable_m, "cable_m", torch.float64, (p.n_ant,) if cable_m is not None else None)
+    if gains is not None and cable_m is not None and gains.shape[0] != cable_m.shape[0]:
+        raise ValueError("gains and cable_m must cover the same antennas")
+    keep = (vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains, cable_m)
     inp = Inputs(vis=_ptr(vis), vis_scale=_ptr(vis_scale), uvw_m=_ptr(uvw_m), freq_hz=_ptr(freq_hz),
-                 flags=_ptr(flags), ant1=_ptr(ant1), ant2=_ptr(ant2), gains=_ptr(gains))
+                 flags=_ptr(flags), ant1=_ptr(ant1), ant2=_ptr(ant2), gains=_ptr(gains),
+                 cable_m=_ptr(cable_m))
     return inp, keep
 
 
@@ -202,13 +207,16 @@ def _vis_type(vis):
 def image_batch(vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None, weighting=NATURAL,
                 norm=NORM_WEIGHTS, flags=None, vis_scale=None, ant1=None, ant2=None, gains=None,
                 chunk_images=None, cols_per_wg=None, rows_wg=None, images=None, weight_sum=None,
-                ws=None, stream=None, times=None, kernel_support=0, kernel_beta=-1.0, phase_lm=(0.0, 0.0)):
+                ws=None, stream=None, times=None, kernel_support=0, kernel_beta=-1.0, phase_lm=(0.0, 0.0),
+                cable_m=None):
     """Dirty images [T*C][M][M] float32 of the cube (blink_image_batch).
 
     Tunables left as None come from the autotuner's cache for this shape.
     ``kernel_support`` W >= 1 grids with a Kaiser-Bessel kernel of W cells
     (shape ``kernel_beta``, < 0 for the default) and corrects the image for it.
     ``phase_lm`` = (l0, m0) rotates the phase centre from zenith to that direction.
+    ``cable_m`` [A] float64 electrical cable lengths (with ``ant1``/``ant2``)
+    applies the cable correction exp(+2 pi i nu (l_ant1 - l_ant2) / c).
     With ``times`` (a KernelTimes) the instrumented twin blink_image_batch_timed
     runs instead: same results, per-kernel-class event timings, host waits.
     """
@@ -216,8 +224,9 @@ def image_batch(vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None, weighting=
     M = grid_n if out_n is None else out_n
     tun = tuning_for(grid_n, M, vis.shape[2], weighting, _vis_type(vis), chunk_images, cols_per_wg, rows_wg)
     p = make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, weighting, norm, gains, **tun,
-                     kernel_support=kernel_support, kernel_beta=kernel_beta, phase_lm=phase_lm)
-    inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains)
+                     kernel_support=kernel_support, kernel_beta=kernel_beta, phase_lm=phase_lm,
+                     cable_m=cable_m)
+    inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains, cable_m)
     n_img, M = p.n_time * p.n_chan, p.out_n
     if images is None:
         images = torch.empty((n_img, M, M), dtype=torch.float32, device=vis.device)
@@ -236,12 +245,13 @@ def image_batch(vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None, weighting=
 
 def grid(vis, uvw_m, freq_hz, *, grid_n, pixscale, weighting=NATURAL, flags=None, vis_scale=None,
          ant1=None, ant2=None, gains=None, counts=True, chunk_images=0, stream=None,
-         kernel_support=0, kernel_beta=-1.0, phase_lm=(0.0, 0.0)):
+         kernel_support=0, kernel_beta=-1.0, phase_lm=(0.0, 0.0), cable_m=None):
     """(weighted grid [T*C][N][N] c64, counts int32 or None, W float32, n_dropped int32)."""
     lib = load_library()
     p = make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, grid_n, weighting, NORM_NONE, gains,
-                     chunk_images, kernel_support=kernel_support, kernel_beta=kernel_beta, phase_lm=phase_lm)
-    inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains)
+                     chunk_images, kernel_support=kernel_support, kernel_beta=kernel_beta, phase_lm=phase_lm,
+                     cable_m=cable_m)
+    inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains, cable_m)
     n_img, N, dev = p.n_time * p.n_chan, grid_n, vis.device
     g = torch.empty((n_img, N, N), dtype=torch.complex64, device=dev)
     c = torch.empty((n_img, N, N), dtype=torch.int32, device=dev) if counts else None

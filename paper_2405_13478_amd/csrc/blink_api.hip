@@ -38,6 +38,8 @@ constexpr int KB_MAX_SUPPORT = 16;
 
 // A phase centre other than zenith asks for the geometric rotation.
 inline bool rotates(const blink_problem* p) { return p->phase_l != 0.0 || p->phase_m != 0.0; }
+// a delay per visibility: geometric rotation or cable lengths
+inline bool delays(const blink_problem* p, const blink_inputs* in) { return rotates(p) || in->cable_m != nullptr; }
 
 // pi sqrt(0.5625 W^2 - 0.8): the Kaiser-Bessel shape for a grid twice the
 // kept image (Beatty, Nishimura and Pauly 2005); negative when W is too small.
@@ -104,7 +106,9 @@ size_t carve(const blink_problem* p, int call, int chunk, char* base, Work* w) {
   x.su = (double*)take(T * B * 8);
   x.sv = (double*)take(T * B * 8);
   x.perm = (int*)take(T * B * 4);
-  if (rotates(p)) x.sd = (double*)take(T * B * 8);
+  // delay table of the phase rotation or cable correction (whether one is
+  // applied depends on the inputs, which the size query does not see)
+  if (call != BLINK_CALL_ADJOINT) x.sd = (double*)take(T * B * 8);
   const size_t n_img = (size_t)p->n_time * (size_t)p->n_chan;
   x.bnd = (int*)take(n_img * (N + 2) * 4);
   x.ncz = (int*)take(n_img * 4);
@@ -163,6 +167,7 @@ blink_status validate_inputs(const blink_problem* p, const blink_inputs* in) {
   if (!in->vis || !in->uvw_m || !in->freq_hz) return BLINK_E_ARG;
   if (p->vis_type != BLINK_VIS_C64 && !in->vis_scale) return BLINK_E_ARG;
   if (in->gains && (!in->ant1 || !in->ant2 || p->n_ant < 1)) return BLINK_E_ARG;
+  if (in->cable_m && (!in->ant1 || !in->ant2 || p->n_ant < 1)) return BLINK_E_ARG;
   return BLINK_OK;
 }
 
@@ -238,11 +243,14 @@ void run_sort(const blink_problem* p, const blink_inputs* in, const Work& w, hip
   s.idx[0] = w.idx[0]; s.idx[1] = w.idx[1];
   s.n_unflagged = w.counters; s.n_valid = w.counters + T;
   s.su = w.su; s.sv = w.sv; s.perm = w.perm;
-  s.sd = w.sd;
-  if (w.sd != nullptr) {
+  s.sd = delays(p, in) ? w.sd : nullptr;
+  if (s.sd != nullptr) {
     s.pl = p->phase_l;
     s.pm = p->phase_m;
     s.pn1 = sqrt(1.0 - p->phase_l * p->phase_l - p->phase_m * p->phase_m) - 1.0;
+    s.cable = in->cable_m;
+    s.ant1 = in->ant1;
+    s.ant2 = in->ant2;
   }
   if (B == 0 || B > SORT_RUN) {
     T_.begin(0);
@@ -288,7 +296,7 @@ ImgArgs make_args(const blink_problem* p, const blink_inputs* in, const Work& w)
   a.ant1 = in->ant1; a.ant2 = in->ant2;
   a.gains = reinterpret_cast<const float2*>(in->gains);
   a.n_ant = p->n_ant;
-  a.su = w.su; a.sv = w.sv; a.perm = w.perm; a.sd = w.sd;
+  a.su = w.su; a.sv = w.sv; a.perm = w.perm; a.sd = delays(p, in) ? w.sd : nullptr;
   a.n_unflagged = w.counters; a.n_valid = w.counters + p->n_time;
   a.bnd = w.bnd; a.ncz = w.ncz; a.wpart = w.wpart; a.kpart = w.kpart; a.wstride = w.wstride;
   a.half = w.half; a.gamma = w.gamma; a.pacc = w.pacc;
@@ -648,6 +656,7 @@ blink_status blink_degrid_adjoint(const blink_problem* p, const blink_inputs* in
   blink_status e = validate_problem(p, BLINK_CALL_ADJOINT);
   if (e != BLINK_OK) return e;
   if ((e = validate_inputs(p, in)) != BLINK_OK) return e;
+  if (in->cable_m) return BLINK_E_UNSUPPORTED;
   const long long n_img = (long long)p->n_time * p->n_chan;
   if (gain_grad && (!in->gains || !in->ant1 || !in->ant2 || p->n_ant < 1)) return BLINK_E_ARG;
   if (n_img > 0 && p->n_bl > 0 && (!image_grad || !vis_grad)) return BLINK_E_ARG;

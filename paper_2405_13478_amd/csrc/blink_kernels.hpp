@@ -61,14 +61,25 @@ struct SortArgs {
   double* su;                    // [T][B] sorted u
   double* sv;                    // [T][B] v in the same order
   int* perm;                     // [T][B] baseline index in the same order
-  double* sd;                    // [T][B] geometric delay in the same order, or null (no rotation)
+  double* sd;                    // [T][B] delay in the same order, or null (no rotation)
   double pl, pm, pn1;            // phase centre l0, m0 and n0 - 1
+  const double* cable;           // [A] electrical cable lengths (m) or null
+  const int* ant1;               // [B] (with cable lengths)
+  const int* ant2;               // [B]
 };
 
 // u l0 + v m0 + w (n0 - 1): the path difference (metres) between the new
 // phase centre and zenith for baseline uvw.
 __device__ __forceinline__ double geo_delay(const double* uvw, double l0, double m0, double n1) {
   return uvw[0] * l0 + uvw[1] * m0 + uvw[2] * n1;
+}
+
+// The delay of baseline b (metres): the geometric term plus, with cable
+// lengths, l_ant1 - l_ant2 (a longer path delays that antenna's voltage).
+__device__ __forceinline__ double baseline_delay(const SortArgs& a, size_t tb, int b) {
+  double d = geo_delay(a.uvw + (tb + b) * 3, a.pl, a.pm, a.pn1);
+  if (a.cable != nullptr) d += a.cable[a.ant1[b]] - a.cable[a.ant2[b]];
+  return d;
 }
 
 __global__ void k_sort_init(int* a, int n) {
@@ -183,7 +194,7 @@ __global__ void __launch_bounds__(1024) k_sort_small(SortArgs a) {
     const int b = si[j];
     a.su[tb + j] = a.uvw[(tb + b) * 3 + 0];
     a.sv[tb + j] = a.uvw[(tb + b) * 3 + 1];
-    if (a.sd != nullptr) a.sd[tb + j] = geo_delay(a.uvw + (tb + b) * 3, a.pl, a.pm, a.pn1);
+    if (a.sd != nullptr) a.sd[tb + j] = baseline_delay(a, tb, b);
     a.perm[tb + j] = b;
   }
   if (threadIdx.x == 0) {
@@ -231,7 +242,7 @@ __global__ void __launch_bounds__(256) k_sort_finish(SortArgs a, int src) {
   const int b = a.idx[src][tb + j];
   a.su[tb + j] = a.uvw[(tb + b) * 3 + 0];
   a.sv[tb + j] = a.uvw[(tb + b) * 3 + 1];
-  if (a.sd != nullptr) a.sd[tb + j] = geo_delay(a.uvw + (tb + b) * 3, a.pl, a.pm, a.pn1);
+  if (a.sd != nullptr) a.sd[tb + j] = baseline_delay(a, tb, b);
   a.perm[tb + j] = b;
   const bool valid = k != KEY_MAX;
   const bool next_invalid = (j + 1 == a.B) || a.key[src][tb + j + 1] == KEY_MAX;

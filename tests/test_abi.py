@@ -58,7 +58,7 @@ def _prob(**kw):
 
 def _inputs(**kw):
     d = dict(vis=FAKE, vis_scale=None, uvw_m=FAKE, freq_hz=FAKE, flags=None, ant1=None,
-             ant2=None, gains=None)
+             ant2=None, gains=None, cable_m=None)
     d.update(kw)
     return B.Inputs(**d)
 
@@ -204,7 +204,25 @@ def test_phase_rotation_has_no_adjoint(lib):
     assert a(ctypes.byref(p), ctypes.byref(_inputs()), FAKE, FAKE, None, None, 0, None) == E_UNSUP
 
 
-def test_phase_rotation_workspace_holds_delays(lib):
+def test_workspace_holds_the_delay_table(lib):
+    # image and grid calls reserve the [T][B] delay table of the phase rotation
+    # and the cable correction whether or not one is applied (cable lengths are
+    # an input, which the size query does not see); with the two sort key
+    # buffers, two index buffers, sorted u, v and order that is 52 B per
+    # baseline and timestep
     p0 = _prob(n_bl=1000)
     p1 = _prob(n_bl=1000, phase_l=0.1)
-    assert lib.blink_workspace_size(ctypes.byref(p1), 1) >= lib.blink_workspace_size(ctypes.byref(p0), 1) + 2 * 1000 * 8
+    for call in (0, 1):
+        s0 = lib.blink_workspace_size(ctypes.byref(p0), call)
+        assert s0 == lib.blink_workspace_size(ctypes.byref(p1), call)
+        assert s0 >= 2 * 1000 * 52
+
+
+def test_cable_correction_validation(lib):
+    # cable lengths need both antenna index arrays and n_ant >= 1
+    assert _image(lib, _prob(), _inputs(cable_m=FAKE)) == E_ARG
+    assert _image(lib, _prob(), _inputs(cable_m=FAKE, ant1=FAKE)) == E_ARG
+    assert _image(lib, _prob(n_ant=0), _inputs(cable_m=FAKE, ant1=FAKE, ant2=FAKE)) == E_ARG
+    a = lib.blink_degrid_adjoint
+    inp = _inputs(cable_m=FAKE, ant1=FAKE, ant2=FAKE)
+    assert a(ctypes.byref(_prob()), ctypes.byref(inp), FAKE, FAKE, None, None, 0, None) == E_UNSUP
