@@ -31,7 +31,7 @@ KB_SUPPORT = 6                 # Kaiser-Bessel support (cells) of the kernel-gri
 ROT_LM = (0.05, 0.03)          # phase centre of the rotation workload (direction cosines)
 CABLE_MAX_M = 500.0            # rotation workload: electrical cable lengths uniform in [0, 500) m
 METRIC = "dirty images/s and visibilities/s at 128 tiles, 1024² grid; % HBM roofline"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_grid_cols_rows_widefield1024.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_grid_cols_half_k_rows_half_widefield1024.json")
 CSRC = os.path.join(ROOT, "paper_2405_13478_amd", "csrc")
 
 
@@ -121,7 +121,7 @@ PROFILE_CMDS = {
 # kernel statistics of the other workloads: (output folder, bench flags, summary file, title)
 EXTRA_STATS = {
     "widefield_kb": ("stats_widefield_kb", "--workload widefield_kb --steps 3 --warmup 1 --no-cpu-baseline",
-                     "k_grid_cols_kb_k_rows_widefield1024_kernel_gridding_kernel_stats.md",
+                     "k_grid_cols_kb_k_rows_half_kb_widefield1024_kernel_stats.md",
                      "widefield 1024^2 -> 512^2 with a 6-cell Kaiser-Bessel gridding kernel, 7,680-image steps"),
     "dynspec": ("stats_dynspec", "--workload dynspec --steps 5 --warmup 1 --no-cpu-baseline",
                 "k_dynspec_100x96_512sq_mean8_kernel_stats.md",
@@ -174,7 +174,7 @@ def summarize(out_dir):
         lines.append(f"| `{r['Name'].replace('|', '/')}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                      f"{100 * float(r['TotalDurationNs']) / tot:.1f}% |")
-    with open(os.path.join(prof, "k_grid_cols_k_rows_widefield1024_kernel_stats.md"), "w") as f:
+    with open(os.path.join(prof, "k_grid_cols_half_k_rows_half_widefield1024_kernel_stats.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
     for k, (d, _, fname, title) in EXTRA_STATS.items():
         if not glob.glob(os.path.join(out_dir, d, "*_kernel_stats.csv")):
