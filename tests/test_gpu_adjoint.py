@@ -75,7 +75,7 @@ def test_adjoint_dot_product_on_gpu():
     assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), 1e-30)
 
 
-def test_autograd_matches_adjoint_and_oracle_fd_gradient():
+def test_autograd_matches_oracle_gradient():
     w, _ = _case("subset64_gains")
     d = inputs(w, with_gains=True)
     vis = d["vis"].clone().requires_grad_(True)
@@ -87,7 +87,8 @@ def test_autograd_matches_adjoint_and_oracle_fd_gradient():
                             weighting=w.weighting, norm=w.norm)
     loss = ((img - target) ** 2).sum()
     loss.backward()
-    # the oracle gradient of the same loss (its adjoint passes the FP64 finite-difference pin)
+    # the oracle gradient of the same loss; the oracle's adjoint is pinned on the CPU by
+    # FP64 central finite differences on this same 16-antenna 64^2 subset
     vnp = d["vis"].cpu().numpy()
     ref_img, _ = oracle.image_batch(vnp, w.uvw_m, w.freq_hz, w.grid_n, w.pixscale, w.out_n,
                                     w.weighting, w.norm, None, w.gains, w.ant1, w.ant2)
@@ -97,4 +98,4 @@ def test_autograd_matches_adjoint_and_oracle_fd_gradient():
     ev = rel_l2(vis.grad.cpu().numpy().view(np.float32), rv.view(np.float64))
     eg = rel_l2(gains.grad.cpu().numpy().view(np.float32), rg.view(np.float64))
     print(f"  autograd vs oracle: vis {ev:.2e} gains {eg:.2e}", flush=True)
-    assert ev <= 1e-4 and eg <= 1e-4
+    assert ev <= 1e-5 and eg <= 1e-5

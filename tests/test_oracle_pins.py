@@ -371,3 +371,54 @@ def test_cost_table_arithmetic():
     # the FFT operation-count model of the cost table: N^2 log2 N^2
     assert round(O.fft_flops_estimate(180)) == 485472
     assert O.fft_flops_estimate(1024) == 1024 ** 2 * 20
+
+
+def test_adjoint_finite_differences_differentiation_subset():
+    """Central finite differences in FP64 on the differentiation setup's
+    16-antenna subset of the 128-tile array (120 baselines, 64^2 grid, one
+    timestep and channel, gains 1 + N(0, 0.05)(1 + i)): loss = ||I - I_model||^2
+    against an image of 50 random point sources. All 32 real gain parameters
+    and 128 visibility components (64 random baselines, real and imaginary
+    parts) match the oracle's adjoint (Sec. 4.2 (ii) gains, V' = g1 conj(g2) V).
+    The loss is quadratic in V, so central differences are exact there up to
+    rounding; for the gains the truncation error is O(h^2)."""
+    from paper_2405_13478_amd import synth
+
+    w = synth.subset_antennas(synth.widefield(1, 1), 16, 64)
+    assert (w.n_ant, w.n_bl, w.grid_n, w.out_n) == (16, 120, 64, 64)
+    vis = synth.visibilities(w).numpy()[0, 0].astype(np.complex128)
+    g = w.gains.astype(np.complex128)
+    u, v, f, n = w.uvw_m[0, :, 0], w.uvw_m[0, :, 1], w.freq_hz[0], w.grid_n
+    rng = np.random.default_rng(44)
+    model = np.zeros((n, n))
+    model.flat[rng.choice(n * n, 50, replace=False)] = rng.uniform(1, 10, 50)
+
+    def image(vv, gg):
+        return O.image_one(vv, u, v, f, n, w.pixscale, n, w.weighting, w.norm,
+                           gains=gg, ant1=w.ant1, ant2=w.ant2)
+
+    def loss(vv, gg):
+        return float(np.sum((image(vv, gg)["image"] - model) ** 2))
+
+    r = image(vis, g)
+    assert r["keep"].all()
+    vg, gg = O.adjoint_one(2 * (r["image"] - model), vis, u, v, f, n, w.pixscale,
+                           w.weighting, w.norm, gains=g, ant1=w.ant1, ant2=w.ant2)
+
+    def fd(fn, x, k, part):
+        h = 1e-6 * max(1.0, abs(x[k]))
+        d = h if part == 0 else 1j * h
+        xp = x.copy(); xp[k] += d
+        xm = x.copy(); xm[k] -= d
+        return (fn(xp) - fn(xm)) / (2 * h)
+
+    def check(fn, x, grad, ks):
+        num = np.array([fd(fn, x, k, p) for k in ks for p in (0, 1)])
+        ana = np.array([(grad[k].real, grad[k].imag)[p] for k in ks for p in (0, 1)])
+        assert np.all(np.abs(num - ana) <= 1e-6 * np.maximum(1.0, np.abs(ana)))
+        assert np.linalg.norm(num - ana) <= 1e-6 * np.linalg.norm(ana)
+        return len(num)
+
+    assert check(lambda q: loss(vis, q), g, gg, range(16)) == 32
+    ks = np.sort(rng.choice(w.n_bl, 64, replace=False))
+    assert check(lambda q: loss(q, g), vis, vg, ks) == 128
