@@ -79,8 +79,8 @@
  *   multiplies its voltage by exp(-2 pi i nu l_a / c0); each V' of baseline
  *   (ant1, ant2) is multiplied by exp(+2 pi i (l_ant1 - l_ant2) nu_c / c0).
  *   The term adds to the geometric delay above (one factor per visibility).
- *   It needs ant1, ant2 (indices < n_ant, not checked on the device) and
- *   n_ant >= 1; blink_degrid_adjoint with cable lengths returns
+ *   It needs ant1, ant2 and n_ant >= 1; an antenna index outside
+ *   [0, n_ant) contributes no cable term (and, with gains, a zero gain); blink_degrid_adjoint with cable lengths returns
  *   BLINK_E_UNSUPPORTED. Per-antenna complex gains (Sec. 4.2 (ii)) are the
  *   `gains` input.
  */

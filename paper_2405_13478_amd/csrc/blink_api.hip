@@ -251,6 +251,7 @@ void run_sort(const blink_problem* p, const blink_inputs* in, const Work& w, hip
     s.cable = in->cable_m;
     s.ant1 = in->ant1;
     s.ant2 = in->ant2;
+    s.n_ant = p->n_ant;
   }
   if (B == 0 || B > SORT_RUN) {
     T_.begin(0);

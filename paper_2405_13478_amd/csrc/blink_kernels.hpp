@@ -66,6 +66,7 @@ struct SortArgs {
   const double* cable;           // [A] electrical cable lengths (m) or null
   const int* ant1;               // [B] (with cable lengths)
   const int* ant2;               // [B]
+  int n_ant;                     // cable length entries; an antenna index outside [0, n_ant) adds 0
 };
 
 // u l0 + v m0 + w (n0 - 1): the path difference (metres) between the new
@@ -76,9 +77,14 @@ __device__ __forceinline__ double geo_delay(const double* uvw, double l0, double
 
 // The delay of baseline b (metres): the geometric term plus, with cable
 // lengths, l_ant1 - l_ant2 (a longer path delays that antenna's voltage).
+// An antenna index outside [0, n_ant) contributes no cable term, as it
+// contributes a zero gain on the gains path.
+__device__ __forceinline__ double cable_len(const SortArgs& a, int i) {
+  return (unsigned)i < (unsigned)a.n_ant ? a.cable[i] : 0.0;
+}
 __device__ __forceinline__ double baseline_delay(const SortArgs& a, size_t tb, int b) {
   double d = geo_delay(a.uvw + (tb + b) * 3, a.pl, a.pm, a.pn1);
-  if (a.cable != nullptr) d += a.cable[a.ant1[b]] - a.cable[a.ant2[b]];
+  if (a.cable != nullptr) d += cable_len(a, a.ant1[b]) - cable_len(a, a.ant2[b]);
   return d;
 }
 
