@@ -25,7 +25,9 @@
  * - Argument errors are detected on the host before anything is enqueued and
  *   leave every output untouched. A failed kernel launch returns BLINK_E_HIP.
  *   Faults during execution surface at the caller's next synchronisation.
- * - No mutable global state: calls are thread-safe.
+ * - No mutable global state, so calls are thread-safe; the one exception is
+ *   blink_image_batch_noalloc, whose per-GPU scratch array is shared by all
+ *   of its calls on that GPU (see there).
  *
  * Geometry and the readings of the paper used throughout
  * ------------------------------------------------------
@@ -200,6 +202,31 @@ blink_status blink_image_batch(const blink_problem* p, const blink_inputs* in,
                                float* images, float* weight_sum,
                                void* workspace, size_t ws_bytes,
                                blink_stream_t stream);
+
+/*
+ * blink_image_batch_noalloc: blink_image_batch for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation). Same arguments without the
+ * workspace, same results bit for bit. Its scratch memory is a fixed
+ * array of BLINK_NOALLOC_SCRATCH_BYTES in the library's code object, one
+ * copy per GPU, held until the process ends; the call itself allocates
+ * nothing. The array of the CURRENT device is used (its address is looked
+ * up once per device on the first call there), so `stream` must belong to
+ * the current device. The cube is imaged in blocks of whole timesteps whose
+ * workspace fits the array, with chunk_images as an upper bound on the
+ * images per internal chunk. Returns BLINK_E_WORKSPACE when the workspace
+ * of one timestep with a single-image chunk exceeds the array (e.g.
+ * N = M = 4096, whose half spectrum alone is 64 MiB per image), BLINK_E_HIP
+ * if the address lookup fails, and the errors of blink_image_batch
+ * otherwise.
+ * Every call on a GPU shares that GPU's array: calls that may overlap on one
+ * GPU (other streams, other host threads) race and must be serialised by
+ * the caller. Nothing in the array needs to be cleared between calls.
+ */
+#define BLINK_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+blink_status blink_image_batch_noalloc(const blink_problem* p, const blink_inputs* in,
+                                       float* images, float* weight_sum,
+                                       blink_stream_t stream);
 
 /*
  * blink_degrid_adjoint: gradients of a real loss L through blink_image_batch,

@@ -25,7 +25,9 @@ STATUS = {0: "BLINK_OK", -1: "BLINK_E_ARG", -2: "BLINK_E_SIZE", -3: "BLINK_E_UNS
 # every symbol include/blink.h declares
 EXPORTS = ("blink_status_string", "blink_supported_n", "blink_workspace_size", "blink_grid",
            "blink_fft2d", "blink_image_batch", "blink_degrid_adjoint", "blink_image_batch_timed",
-           "blink_dynamic_spectra", "blink_correlate")
+           "blink_dynamic_spectra", "blink_correlate", "blink_image_batch_noalloc")
+
+NOALLOC_SCRATCH_BYTES = 64 << 20       # BLINK_NOALLOC_SCRATCH_BYTES
 
 REF_NONE, REF_MEAN, REF_MODEL = 0, 1, 2
 REF_MAX_LEN = 128
@@ -88,6 +90,8 @@ def load_library(path: str | None = None):
     lib.blink_image_batch.restype = i32
     lib.blink_degrid_adjoint.argtypes = [P, I, vp, vp, vp, vp, sz, vp]
     lib.blink_degrid_adjoint.restype = i32
+    lib.blink_image_batch_noalloc.argtypes = [P, I, vp, vp, vp]
+    lib.blink_image_batch_noalloc.restype = i32
     lib.blink_image_batch_timed.argtypes = [P, I, vp, vp, vp, sz, vp, ctypes.POINTER(KernelTimes)]
     lib.blink_image_batch_timed.restype = i32
     lib.blink_dynamic_spectra.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp, vp]
@@ -240,6 +244,26 @@ def image_batch(vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None, weighting=
         _check(lib.blink_image_batch(*args), "blink_image_batch")
     else:
         _check(lib.blink_image_batch_timed(*args, ctypes.byref(times)), "blink_image_batch_timed")
+    return images
+
+
+def image_batch_noalloc(images, vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None,
+                        weighting=NATURAL, norm=NORM_WEIGHTS, flags=None, vis_scale=None, ant1=None,
+                        ant2=None, gains=None, chunk_images=0, cols_per_wg=0, rows_wg=0,
+                        weight_sum=None, stream=None):
+    """blink_image_batch_noalloc into caller-allocated ``images`` [T*C][M][M]
+    (and ``weight_sum`` [T*C]): the library allocates nothing; its scratch is a
+    fixed per-GPU array. Tunables are passed as given (0 = library default)."""
+    lib = load_library()
+    p = make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, weighting, norm, gains,
+                     chunk_images, cols_per_wg, rows_wg)
+    inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains)
+    n_img, M = p.n_time * p.n_chan, p.out_n
+    _dev(images, "images", torch.float32, (n_img, M, M))
+    _dev(weight_sum, "weight_sum", torch.float32, (n_img,))
+    _check(lib.blink_image_batch_noalloc(ctypes.byref(p), ctypes.byref(inp), _ptr(images),
+                                         _ptr(weight_sum), _stream(stream)),
+           "blink_image_batch_noalloc")
     return images
 
 

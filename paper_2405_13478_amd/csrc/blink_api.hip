@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -14,6 +15,13 @@
 #include "blink_kernels.hpp"
 
 using namespace blink;
+
+// Workspace of blink_image_batch_noalloc: a fixed array in the code object,
+// one copy on every GPU the library runs on, held until the process ends.
+// Host code never passes `scratch` itself to a kernel (on the host the name
+// is only a stand-in): it takes the device address from hipGetSymbolAddress
+// once per device and uses that.
+static __device__ __align__(256) unsigned char scratch[BLINK_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -648,6 +656,94 @@ blink_status blink_image_batch_timed(const blink_problem* p, const blink_inputs*
   blink_status e = image_batch_impl(p, in, images, weight_sum, workspace, ws_bytes, stream, &tm);
   const blink_status c = tm.collect(times);
   return e != BLINK_OK ? e : c;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+void* noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the current device's scratch array, looked up once per
+// device (with that device current) and kept.
+blink_status scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return BLINK_E_HIP;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return BLINK_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(noalloc_mu);
+  if (noalloc_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) return BLINK_E_HIP;
+    noalloc_ptr[dev] = ptr;
+  }
+  *out = noalloc_ptr[dev];
+  return BLINK_OK;
+}
+
+// Workspace bytes of an image call on tb timesteps of p with `chunk` images
+// per internal chunk.
+size_t block_need(const blink_problem* p, int tb, int chunk) {
+  blink_problem q = *p;
+  q.n_time = tb;
+  return carve(&q, BLINK_CALL_IMAGE, chunk, nullptr, nullptr);
+}
+
+// Splits the cube into blocks of whole timesteps whose workspace fits the
+// scratch array and picks the largest chunk that fits with them. Returns
+// false when one timestep with a chunk of one image does not fit.
+bool plan_noalloc(const blink_problem* p, int* tb, int* chunk) {
+  const size_t cap = BLINK_NOALLOC_SCRATCH_BYTES;
+  const size_t per_img = (size_t)(p->grid_n / 2) * (size_t)p->out_n * 8;   // half spectrum of one image
+  int t = p->n_time;
+  while (t > 1 && block_need(p, t, 1) > cap) t = (t + 1) / 2;
+  if (block_need(p, t, 1) > cap) return false;
+  const size_t fixed = block_need(p, t, 0);
+  long long ch = (long long)((cap - fixed) / (per_img + 255));   // al() adds at most 255 bytes
+  ch = std::min<long long>(ch, (long long)t * p->n_chan);
+  ch = std::min<long long>(ch, MAX_GRID_Y);
+  if (p->chunk_images > 0) ch = std::min<long long>(ch, p->chunk_images);
+  ch = std::max<long long>(ch, 1);
+  while (ch > 1 && block_need(p, t, (int)ch) > cap) --ch;
+  *tb = t;
+  *chunk = (int)ch;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+blink_status blink_image_batch_noalloc(const blink_problem* p, const blink_inputs* in, float* images,
+                                       float* weight_sum, blink_stream_t stream) {
+  blink_status e = validate_problem(p, BLINK_CALL_IMAGE);
+  if (e != BLINK_OK) return e;
+  if ((e = validate_inputs(p, in)) != BLINK_OK) return e;
+  const long long n_img = (long long)p->n_time * p->n_chan;
+  if (n_img > 0 && !images) return BLINK_E_ARG;
+  if (n_img == 0) return BLINK_OK;
+  int tb = 0, chunk = 0;
+  if (!plan_noalloc(p, &tb, &chunk)) return BLINK_E_WORKSPACE;
+  void* ws = nullptr;
+  if ((e = scratch_address(&ws)) != BLINK_OK) return e;
+  const size_t B = (size_t)p->n_bl, C = (size_t)p->n_chan, MM = (size_t)p->out_n * p->out_n;
+  const size_t vsz = p->vis_type == BLINK_VIS_C64 ? 8 : 4;
+  blink_problem q = *p;
+  q.chunk_images = chunk;
+  for (int t0 = 0; t0 < p->n_time; t0 += tb) {
+    q.n_time = std::min(tb, p->n_time - t0);
+    const size_t i0 = (size_t)t0 * C;                      // first image of the block
+    blink_inputs s = *in;
+    s.vis = static_cast<const char*>(in->vis) + i0 * B * vsz;
+    s.uvw_m = in->uvw_m + (size_t)t0 * B * 3;
+    if (in->flags) s.flags = in->flags + (size_t)t0 * B;
+    Timer off;
+    e = image_batch_impl(&q, &s, images + i0 * MM, weight_sum ? weight_sum + i0 : nullptr, ws,
+                         BLINK_NOALLOC_SCRATCH_BYTES, stream, &off);
+    if (e != BLINK_OK) return e;
+  }
+  return BLINK_OK;
 }
 
 blink_status blink_degrid_adjoint(const blink_problem* p, const blink_inputs* in,

@@ -226,3 +226,25 @@ def test_cable_correction_validation(lib):
     a = lib.blink_degrid_adjoint
     inp = _inputs(cable_m=FAKE, ant1=FAKE, ant2=FAKE)
     assert a(ctypes.byref(_prob()), ctypes.byref(inp), FAKE, FAKE, None, None, 0, None) == E_UNSUP
+
+
+def _noalloc(lib, p, inp, images=FAKE):
+    return lib.blink_image_batch_noalloc(ctypes.byref(p) if p is not None else None,
+                                         ctypes.byref(inp) if inp is not None else None,
+                                         images, None, None)
+
+
+def test_noalloc_validation(lib):
+    # the entry point without a workspace: the same argument checks as
+    # blink_image_batch, all on the host before the scratch array is touched
+    assert _noalloc(lib, None, _inputs()) == E_ARG
+    assert _noalloc(lib, _prob(), None) == E_ARG
+    assert _noalloc(lib, _prob(), _inputs(vis=None)) == E_ARG
+    assert _noalloc(lib, _prob(), _inputs(), images=None) == E_ARG
+    assert _noalloc(lib, _prob(grid_n=63), _inputs()) == E_SIZE
+    assert _noalloc(lib, _prob(grid_n=1000), _inputs()) == E_UNSUP
+    assert _noalloc(lib, _prob(n_time=0), _inputs(vis=None, uvw_m=None, freq_hz=None)) == E_OK
+    # one image whose workspace exceeds the 64 MiB array: its half spectrum
+    # alone is 2048 x 4096 x 8 B = 64 MiB
+    assert B.NOALLOC_SCRATCH_BYTES == 64 << 20
+    assert _noalloc(lib, _prob(n_time=1, n_chan=1, grid_n=4096, out_n=4096), _inputs()) == E_WS
