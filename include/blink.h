@@ -75,16 +75,16 @@
  *   centre. (u, v, w) are not re-projected: the image stays on the zenith
  *   tangent plane, shifted by (l0, m0). The delay is formed in double at the
  *   sort, the phase in cycles in double, its sine and cosine in float.
- *   blink_degrid_adjoint with a rotation returns BLINK_E_UNSUPPORTED.
+ *   blink_degrid_adjoint applies the conjugate factor to the gradients.
  * - Cable correction (blink_inputs.cable_m != NULL; Sec. 4.2 (i)): antenna
  *   a's signal path is longer by the electrical length l_a metres, which
  *   multiplies its voltage by exp(-2 pi i nu l_a / c0); each V' of baseline
  *   (ant1, ant2) is multiplied by exp(+2 pi i (l_ant1 - l_ant2) nu_c / c0).
  *   The term adds to the geometric delay above (one factor per visibility).
  *   It needs ant1, ant2 and n_ant >= 1; an antenna index outside
- *   [0, n_ant) contributes no cable term (and, with gains, a zero gain); blink_degrid_adjoint with cable lengths returns
- *   BLINK_E_UNSUPPORTED. Per-antenna complex gains (Sec. 4.2 (ii)) are the
- *   `gains` input.
+ *   [0, n_ant) contributes no cable term (and, with gains, a zero gain).
+ *   blink_degrid_adjoint applies the conjugate factor to the gradients.
+ *   Per-antenna complex gains (Sec. 4.2 (ii)) are the `gains` input.
  */
 #ifndef BLINK_H
 #define BLINK_H
@@ -232,16 +232,24 @@ blink_status blink_image_batch_noalloc(const blink_problem* p, const blink_input
  * blink_degrid_adjoint: gradients of a real loss L through blink_image_batch,
  * given image_grad = dL/d(images) [T*C][M][M] float:
  *   vis_grad[t][c][b]  = dL/dRe V + i dL/dIm V   (blink_c32, all baselines;
- *                        zero for flagged or dropped ones);
+ *                        zero for flagged or dropped ones; with FP16/BF16
+ *                        storage, the gradient with respect to the
+ *                        dequantised V);
  *   gain_grad[a]       = dL/dRe g + i dL/dIm g   (NULL to skip; needs gains,
  *                        ant1, ant2).
+ * weight_sum [T*C] float: the weight sums W that blink_image_batch returned
+ * for the same problem and inputs, or NULL, in which case they are counted
+ * again from the baseline lists (device memory, not checked: other values
+ * scale the gradient of each image by their ratio to the true W).
  * The map V -> image is linear (W and the counts depend only on geometry and
  * flags), so this is the exact adjoint: zero-pad, 1/W, inverse shift, forward
- * transform, cell weight, gather at +k and -k (degridding). C64 only.
+ * transform, cell weight, gather at +k and -k (degridding), times the
+ * conjugate of the rotation / cable factor when one is applied. Nearest-cell
+ * gridding only (kernel_support > 0 returns BLINK_E_UNSUPPORTED).
  */
 blink_status blink_degrid_adjoint(const blink_problem* p, const blink_inputs* in,
-                                  const float* image_grad, blink_c32* vis_grad,
-                                  blink_c32* gain_grad, void* workspace,
+                                  const float* image_grad, const float* weight_sum,
+                                  blink_c32* vis_grad, blink_c32* gain_grad, void* workspace,
                                   size_t ws_bytes, blink_stream_t stream);
 
 /*

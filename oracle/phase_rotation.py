@@ -73,3 +73,35 @@ def image_batch_rotated(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, weighting,
         out.append(r["image"])
         ws.append(r["W"])
     return np.stack(out), np.asarray(ws)
+
+
+def adjoint_batch_rotated(image_grad, vis, uvw_m, freq_hz, grid_n, pixscale, weighting, norm, l0, m0,
+                          flags=None, gains=None, ant1=None, ant2=None, cable_m=None):
+    """Gradients (vis_grad [T][C][B], gain_grad [A] or None) of sum(images *
+    image_grad) through the rotated imaging of image_batch_rotated.
+
+    Per image the imager sees U = p V with p = exp(+2 pi i d nu / c) (|p| = 1,
+    fixed by the geometry), then applies the gains as for any input. So the
+    gain gradient is the plain adjoint's with U in place of V, and the chain
+    rule through U = p V (convention grad z = dL/dx + i dL/dy) multiplies the
+    gradient with respect to U by conj(p).
+    """
+    from .blink_oracle import adjoint_one
+
+    T, C, B = vis.shape
+    vg = np.zeros((T, C, B), dtype=np.complex128)
+    gg = None if gains is None else np.zeros(len(gains), dtype=np.complex128)
+    for t in range(T):
+        for c in range(C):
+            d = geometric_delay(uvw_m[t], l0, m0)
+            if cable_m is not None:
+                d = d + cable_delay(cable_m, ant1, ant2)
+            p = np.exp(2j * np.pi * d * (np.float64(freq_hz[c]) / C_LIGHT))
+            u = np.asarray(vis[t, c], dtype=np.complex128) * p
+            gu, g_ = adjoint_one(image_grad[t * C + c], u, uvw_m[t, :, 0], uvw_m[t, :, 1], freq_hz[c],
+                                 grid_n, pixscale, weighting, norm, None if flags is None else flags[t],
+                                 gains, ant1, ant2)
+            vg[t, c] = np.conj(p) * gu
+            if gg is not None:
+                gg += g_
+    return vg, gg

@@ -88,7 +88,7 @@ def load_library(path: str | None = None):
     lib.blink_fft2d.restype = i32
     lib.blink_image_batch.argtypes = [P, I, vp, vp, vp, sz, vp]
     lib.blink_image_batch.restype = i32
-    lib.blink_degrid_adjoint.argtypes = [P, I, vp, vp, vp, vp, sz, vp]
+    lib.blink_degrid_adjoint.argtypes = [P, I, vp, vp, vp, vp, vp, sz, vp]
     lib.blink_degrid_adjoint.restype = i32
     lib.blink_image_batch_noalloc.argtypes = [P, I, vp, vp, vp]
     lib.blink_image_batch_noalloc.restype = i32
@@ -305,20 +305,30 @@ def fft2d(x, sign=+1, out=None, stream=None):
 
 def degrid_adjoint(image_grad, vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None,
                    weighting=NATURAL, norm=NORM_WEIGHTS, flags=None, ant1=None, ant2=None,
-                   gains=None, want_gain_grad=True, chunk_images=0, stream=None):
-    """(vis_grad [T][C][B] c64, gain_grad [A] c64 or None) of a loss with dL/dimages = image_grad."""
+                   gains=None, want_gain_grad=True, chunk_images=0, stream=None, weight_sum=None,
+                   vis_scale=None, phase_lm=(0.0, 0.0), cable_m=None):
+    """(vis_grad [T][C][B] c64, gain_grad [A] c64 or None) of a loss with dL/dimages = image_grad.
+
+    ``weight_sum`` [T*C] float32: the forward call's weight sums (skips
+    counting them again). With FP16/BF16 ``vis`` (and ``vis_scale``) the
+    gradient is with respect to the dequantised visibilities. ``phase_lm`` and
+    ``cable_m`` must be those of the forward call.
+    """
     lib = load_library()
-    p = make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, weighting, norm, gains, chunk_images)
-    inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, None, ant1, ant2, gains)
+    p = make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, weighting, norm, gains, chunk_images,
+                     phase_lm=phase_lm, cable_m=cable_m)
+    inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains, cable_m)
     n_img, M = p.n_time * p.n_chan, p.out_n
+    T, C, B = p.n_time, p.n_chan, p.n_bl
     _dev(image_grad, "image_grad", torch.float32, (n_img, M, M))
-    vg = torch.empty(vis.shape, dtype=torch.complex64, device=vis.device)
+    _dev(weight_sum, "weight_sum", torch.float32, (n_img,))
+    vg = torch.empty((T, C, B), dtype=torch.complex64, device=vis.device)
     gg = None
     if gains is not None and want_gain_grad:
         gg = torch.empty(gains.shape, dtype=torch.complex64, device=vis.device)
     ws = workspace(p, CALL_ADJOINT, vis.device)
-    code = lib.blink_degrid_adjoint(ctypes.byref(p), ctypes.byref(inp), _ptr(image_grad), _ptr(vg),
-                                    _ptr(gg), _ptr(ws) if ws.numel() else None, ws.numel(),
+    code = lib.blink_degrid_adjoint(ctypes.byref(p), ctypes.byref(inp), _ptr(image_grad), _ptr(weight_sum),
+                                    _ptr(vg), _ptr(gg), _ptr(ws) if ws.numel() else None, ws.numel(),
                                     _stream(stream))
     _check(code, "blink_degrid_adjoint")
     return vg, gg
@@ -370,33 +380,37 @@ class BlinkImage(torch.autograd.Function):
     """Differentiable dirty imaging: images = blink_image_batch(g[a1] conj(g[a2]) V).
 
     Gradients flow to the complex64 visibilities and the per-antenna gains
-    through the hand-written adjoint (degridding + forward transforms).
+    through the hand-written adjoint (degridding + forward transforms), which
+    reuses the forward call's weight sums.
     """
 
     @staticmethod
     def forward(ctx, vis, gains, uvw_m, freq_hz, ant1, ant2, flags, grid_n, pixscale, out_n,
-                weighting, norm):
-        ctx.save_for_backward(vis, gains, uvw_m, freq_hz, ant1, ant2, flags)
-        ctx.cfg = (grid_n, pixscale, out_n, weighting, norm)
-        return image_batch(vis, uvw_m, freq_hz, grid_n=grid_n, pixscale=pixscale, out_n=out_n,
-                           weighting=weighting, norm=norm, flags=flags, ant1=ant1, ant2=ant2,
-                           gains=gains)
+                weighting, norm, phase_lm=(0.0, 0.0), cable_m=None):
+        wsum = torch.empty((vis.shape[0] * vis.shape[1],), dtype=torch.float32, device=vis.device)
+        img = image_batch(vis, uvw_m, freq_hz, grid_n=grid_n, pixscale=pixscale, out_n=out_n,
+                          weighting=weighting, norm=norm, flags=flags, ant1=ant1, ant2=ant2,
+                          gains=gains, weight_sum=wsum, phase_lm=phase_lm, cable_m=cable_m)
+        ctx.save_for_backward(vis, gains, uvw_m, freq_hz, ant1, ant2, flags, wsum, cable_m)
+        ctx.cfg = (grid_n, pixscale, out_n, weighting, norm, phase_lm)
+        return img
 
     @staticmethod
     def backward(ctx, grad_images):
-        vis, gains, uvw_m, freq_hz, ant1, ant2, flags = ctx.saved_tensors
-        grid_n, pixscale, out_n, weighting, norm = ctx.cfg
+        vis, gains, uvw_m, freq_hz, ant1, ant2, flags, wsum, cable_m = ctx.saved_tensors
+        grid_n, pixscale, out_n, weighting, norm, phase_lm = ctx.cfg
         vg, gg = degrid_adjoint(grad_images.contiguous().float(), vis, uvw_m, freq_hz,
                                 grid_n=grid_n, pixscale=pixscale, out_n=out_n,
                                 weighting=weighting, norm=norm, flags=flags, ant1=ant1,
                                 ant2=ant2, gains=gains,
-                                want_gain_grad=gains is not None and ctx.needs_input_grad[1])
+                                want_gain_grad=gains is not None and ctx.needs_input_grad[1],
+                                weight_sum=wsum, phase_lm=phase_lm, cable_m=cable_m)
         return (vg if ctx.needs_input_grad[0] else None, gg, None, None, None, None, None,
-                None, None, None, None, None)
+                None, None, None, None, None, None, None)
 
 
 def blink_image(vis, gains, uvw_m, freq_hz, ant1, ant2, *, grid_n, pixscale, out_n=None,
-                weighting=NATURAL, norm=NORM_WEIGHTS, flags=None):
+                weighting=NATURAL, norm=NORM_WEIGHTS, flags=None, phase_lm=(0.0, 0.0), cable_m=None):
     """Functional form of BlinkImage."""
     return BlinkImage.apply(vis, gains, uvw_m, freq_hz, ant1, ant2, flags, grid_n, pixscale,
-                            grid_n if out_n is None else out_n, weighting, norm)
+                            grid_n if out_n is None else out_n, weighting, norm, phase_lm, cable_m)

@@ -76,6 +76,7 @@ struct Work {
   double* sv;
   int* perm;
   double* sd;         // sorted geometric delays, only with a phase rotation
+  double* vmax;       // [T] largest |v| of the usable baselines (image call)
   int* bnd;
   int* ncz;
   int* wpart;
@@ -116,7 +117,8 @@ size_t carve(const blink_problem* p, int call, int chunk, char* base, Work* w) {
   x.perm = (int*)take(T * B * 4);
   // delay table of the phase rotation or cable correction (whether one is
   // applied depends on the inputs, which the size query does not see)
-  if (call != BLINK_CALL_ADJOINT) x.sd = (double*)take(T * B * 8);
+  x.sd = (double*)take(T * B * 8);
+  if (call == BLINK_CALL_IMAGE) x.vmax = (double*)take(T * 8);
   const size_t n_img = (size_t)p->n_time * (size_t)p->n_chan;
   x.bnd = (int*)take(n_img * (N + 2) * 4);
   x.ncz = (int*)take(n_img * 4);
@@ -161,10 +163,8 @@ blink_status validate_problem(const blink_problem* p, int call) {
   if (T * C > INT32_MAX || T * B > INT32_MAX) return BLINK_E_SIZE;
   if ((double)T * C * B > 9.0e18 || (double)T * C * N * N > 9.0e18) return BLINK_E_SIZE;
   if (!n_supported(p->grid_n)) return BLINK_E_UNSUPPORTED;
-  if (call == BLINK_CALL_ADJOINT && p->vis_type != BLINK_VIS_C64) return BLINK_E_UNSUPPORTED;
   if (p->kernel_support > 0 && (p->weighting != BLINK_NATURAL || call == BLINK_CALL_ADJOINT))
     return BLINK_E_UNSUPPORTED;
-  if (rotates(p) && call == BLINK_CALL_ADJOINT) return BLINK_E_UNSUPPORTED;
   return BLINK_OK;
 }
 
@@ -307,6 +307,7 @@ ImgArgs make_args(const blink_problem* p, const blink_inputs* in, const Work& w)
   a.n_ant = p->n_ant;
   a.su = w.su; a.sv = w.sv; a.perm = w.perm; a.sd = delays(p, in) ? w.sd : nullptr;
   a.n_unflagged = w.counters; a.n_valid = w.counters + p->n_time;
+  a.vmax = w.vmax;
   a.bnd = w.bnd; a.ncz = w.ncz; a.wpart = w.wpart; a.kpart = w.kpart; a.wstride = w.wstride;
   a.half = w.half; a.gamma = w.gamma; a.pacc = w.pacc;
   a.kw = p->kernel_support;
@@ -330,7 +331,8 @@ void launch_cols_image(ImgArgs& a, int n, hipStream_t st) {
 template <int N, int CPW, bool UNI>
 void launch_cols_half(ImgArgs& a, int n, hipStream_t st) {
   using C_ = ColsHalf<N, CPW, UNI>;
-  a.wtiles = a.ntiles = (int)cdiv(N / 2, CPW);
+  a.ntiles = (int)cdiv(N / 2, CPW);
+  a.wtiles = N / 2;                       // one partial per column
   const dim3 g1((unsigned)(cdiv(n, 8) * 8LL * a.ntiles));
   hipLaunchKernelGGL((k_grid_cols_half<N, CPW, UNI>), g1, dim3(C_::THREADS), C_::LDS, st, a);
 }
@@ -413,7 +415,8 @@ blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t s
   if (cols_lds<N>(cpw, uni, kb) > LDS_PER_CU) return BLINK_E_UNSUPPORTED;
   const size_t rows_lds = rows_lds_base<N>() + (kb ? (size_t)p->out_n * sizeof(float) : 0);
   if (rows_lds > LDS_PER_CU) return BLINK_E_UNSUPPORTED;
-  a.wtiles = (int)cdiv(N / 2, cpw);
+  // partials per image: one per column (half-length column kernel) or per tile
+  a.wtiles = cols_half<N>() && !kb ? N / 2 : (int)cdiv(N / 2, cpw);
   T_.begin(1);
   hipLaunchKernelGGL(k_bounds, dim3((unsigned)n_img), dim3(256), 0, st, a);
   T_.end();
@@ -481,12 +484,16 @@ blink_status adjoint_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t
   for (long long i0 = 0; i0 < n_img; i0 += chunk) {
     const int n = (int)std::min<long long>(chunk, n_img - i0);
     a.img0 = (int)i0; a.nimg = n;
-    const dim3 gw(cdiv(N / 2, Cols<N>::CPW), n);
-    const size_t ldsw = uni ? (size_t)Cols<N>::CPW * N * sizeof(int) : 0;
-    if (uni)
-      hipLaunchKernelGGL((k_weights<N, true>), gw, dim3(Cols<N>::THREADS), ldsw, st, a);
-    else
-      hipLaunchKernelGGL((k_weights<N, false>), gw, dim3(Cols<N>::THREADS), ldsw, st, a);
+    // W from the forward call's weight sums when the caller passes them, else
+    // counted again from the sorted lists
+    if (a.wsum_in == nullptr) {
+      const dim3 gw(cdiv(N / 2, Cols<N>::CPW), n);
+      const size_t ldsw = uni ? (size_t)Cols<N>::CPW * N * sizeof(int) : 0;
+      if (uni)
+        hipLaunchKernelGGL((k_weights<N, true>), gw, dim3(Cols<N>::THREADS), ldsw, st, a);
+      else
+        hipLaunchKernelGGL((k_weights<N, false>), gw, dim3(Cols<N>::THREADS), ldsw, st, a);
+    }
     const dim3 g2(cdiv(p->out_n / 2, Rows<N>::PPW), n);
     hipLaunchKernelGGL((k_rows_adj<N>), g2, dim3(Rows<N>::THREADS), Rows<N>::LDS, st, a);
     // flagged and dropped baselines are never visited: their gradients are zero
@@ -631,7 +638,14 @@ static blink_status image_batch_impl(const blink_problem* p, const blink_inputs*
   Work w{};
   carve(p, BLINK_CALL_IMAGE, chunk, static_cast<char*>(workspace), &w);
   run_sort(p, in, w, st, tm);
+  if (p->n_bl > 0) {
+    tm->begin(0);
+    hipLaunchKernelGGL(k_vmax, dim3((unsigned)p->n_time), dim3(256), 0, st, w.sv, w.counters + p->n_time,
+                       p->n_bl, w.vmax);
+    tm->end();
+  }
   ImgArgs a = make_args(p, in, w);
+  if (p->n_bl == 0) a.vmax = nullptr;
   a.images = images;
   a.weight_sum = weight_sum;
 #define BLINK_IMAGE_CALL(n) image_n<n>(p, a, chunk, st, tm)
@@ -747,13 +761,12 @@ blink_status blink_image_batch_noalloc(const blink_problem* p, const blink_input
 }
 
 blink_status blink_degrid_adjoint(const blink_problem* p, const blink_inputs* in,
-                                  const float* image_grad, blink_c32* vis_grad,
-                                  blink_c32* gain_grad, void* workspace, size_t ws_bytes,
-                                  blink_stream_t stream) {
+                                  const float* image_grad, const float* weight_sum,
+                                  blink_c32* vis_grad, blink_c32* gain_grad, void* workspace,
+                                  size_t ws_bytes, blink_stream_t stream) {
   blink_status e = validate_problem(p, BLINK_CALL_ADJOINT);
   if (e != BLINK_OK) return e;
   if ((e = validate_inputs(p, in)) != BLINK_OK) return e;
-  if (in->cable_m) return BLINK_E_UNSUPPORTED;
   const long long n_img = (long long)p->n_time * p->n_chan;
   if (gain_grad && (!in->gains || !in->ant1 || !in->ant2 || p->n_ant < 1)) return BLINK_E_ARG;
   if (n_img > 0 && p->n_bl > 0 && (!image_grad || !vis_grad)) return BLINK_E_ARG;
@@ -776,6 +789,7 @@ blink_status blink_degrid_adjoint(const blink_problem* p, const blink_inputs* in
   run_sort(p, in, w, st);
   ImgArgs a = make_args(p, in, w);
   a.image_grad = image_grad;
+  a.wsum_in = weight_sum;
   a.vis_grad = reinterpret_cast<float2*>(vis_grad);
   a.gain_grad = reinterpret_cast<float2*>(gain_grad);
 #define BLINK_ADJ_CALL(n) adjoint_n<n>(p, a, chunk, st)

@@ -135,11 +135,49 @@ __device__ __forceinline__ void dft8(float2* a) {
   for (int i = 0; i < 8; ++i) a[i] = b[i];
 }
 
-// radix 16 as 4 x 4: x[4 n1 + n2] -> DFT4 over n1, twiddle w16^(n2 k1), DFT4 over n2
-template <int SIGN>
+// Complex add / subtract of operands that may be known zero at compile time
+// (ZA: a is zero, ZB: b is zero): the known-zero terms cost nothing.
+template <bool ZA, bool ZB>
+__device__ __forceinline__ float2 zadd(float2 a, float2 b) {
+  if constexpr (ZA && ZB) return make_float2(0.f, 0.f);
+  else if constexpr (ZA) return b;
+  else if constexpr (ZB) return a;
+  else return cadd(a, b);
+}
+template <bool ZA, bool ZB>
+__device__ __forceinline__ float2 zsub(float2 a, float2 b) {
+  if constexpr (ZA && ZB) return make_float2(0.f, 0.f);
+  else if constexpr (ZA) return make_float2(-b.x, -b.y);
+  else if constexpr (ZB) return a;
+  else return csub(a, b);
+}
+
+// dft4 with inputs Z0..Z3 known to be zero
+template <int SIGN, bool Z0, bool Z1, bool Z2, bool Z3>
+__device__ __forceinline__ void dft4z(float2& a0, float2& a1, float2& a2, float2& a3) {
+  const float2 s02 = zadd<Z0, Z2>(a0, a2), d02 = zsub<Z0, Z2>(a0, a2);
+  const float2 s13 = zadd<Z1, Z3>(a1, a3), d13 = mul_si<SIGN>(zsub<Z1, Z3>(a1, a3));
+  constexpr bool ZS = Z0 && Z2, ZD = Z1 && Z3;
+  a0 = zadd<ZS, ZD>(s02, s13);
+  a2 = zsub<ZS, ZD>(s02, s13);
+  a1 = zadd<ZS, ZD>(d02, d13);
+  a3 = zsub<ZS, ZD>(d02, d13);
+}
+
+// radix 16 as 4 x 4: x[4 n1 + n2] -> DFT4 over n1, twiddle w16^(n2 k1), DFT4 over n2.
+// ZB: the inputs x[8 - ZB/2 .. 8 + ZB/2) are known to be zero (a transform's
+// first stage whose middle input rows are empty); they are neither read nor
+// added. Every other term is added exactly as in the full codelet, so the
+// outputs are the same numbers.
+template <int SIGN, int ZB = 0>
 __device__ __forceinline__ void dft16(float2* a) {
-#pragma unroll
-  for (int n2 = 0; n2 < 4; ++n2) dft4<SIGN>(a[n2], a[n2 + 4], a[n2 + 8], a[n2 + 12]);
+  static_assert(ZB % 2 == 0 && ZB >= 0 && ZB <= 8, "zero band of the radix-16 codelet");
+  constexpr int zlo = 8 - ZB / 2, zhi = 8 + ZB / 2;
+  static_for<0, 4>([&](auto nc) {
+    constexpr int n2 = decltype(nc)::value;
+    dft4z<SIGN, (n2 >= zlo && n2 < zhi), (n2 + 4 >= zlo && n2 + 4 < zhi), (n2 + 8 >= zlo && n2 + 8 < zhi),
+          (n2 + 12 >= zlo && n2 + 12 < zhi)>(a[n2], a[n2 + 4], a[n2 + 8], a[n2 + 12]);
+  });
   // a[n2 + 4 k1] now holds DFT4 output k1 of column n2; twiddle by w16^(n2 k1)
   a[5] = mul_cs<SIGN>(a[5], kc::C8, kc::S8);      // n2=1 k1=1 : w^1
   a[9] = mul_cs<SIGN>(a[9], kc::R2, kc::R2);      // n2=1 k1=2 : w^2
@@ -162,14 +200,15 @@ __device__ __forceinline__ void dft16(float2* a) {
   for (int i = 0; i < 16; ++i) a[i] = b[i];
 }
 
-template <int R, int SIGN>
+template <int R, int SIGN, int ZB = 0>
 __device__ __forceinline__ void dft(float2* a) {
+  static_assert(ZB == 0 || R == 16, "zero band only in the radix-16 codelet");
   if constexpr (R == 2) dft2<SIGN>(a[0], a[1]);
   else if constexpr (R == 3) dft3<SIGN>(a[0], a[1], a[2]);
   else if constexpr (R == 4) dft4<SIGN>(a[0], a[1], a[2], a[3]);
   else if constexpr (R == 5) dft5<SIGN>(a);
   else if constexpr (R == 8) dft8<SIGN>(a);
-  else if constexpr (R == 16) dft16<SIGN>(a);
+  else if constexpr (R == 16) dft16<SIGN, ZB>(a);
   else static_assert(R == 2, "unsupported radix");
 }
 
@@ -425,9 +464,10 @@ __host__ __device__ constexpr bool plan_even(int n) {
 }
 
 // Twiddle and DFT of the butterflies held in registers (no LDS traffic).
-template <int N, int R, int NS, int SIGN>
+template <int N, int R, int NS, int SIGN, int ZB = 0>
 __device__ __forceinline__ void stage_compute(int lane, const float2* __restrict__ tw,
                                               float2 (&v)[(N / R + WAVE - 1) / WAVE][R]) {
+  static_assert(ZB == 0 || NS == 1, "a zero band only on the first stage's inputs");
   constexpr int NB = N / R;
   constexpr int PER = (NB + WAVE - 1) / WAVE;
 #pragma unroll
@@ -444,7 +484,7 @@ __device__ __forceinline__ void stage_compute(int lane, const float2* __restrict
           v[p][r] = cmul(v[p][r], w);
         }
       }
-      dft<R, SIGN>(v[p]);
+      dft<R, SIGN, ZB>(v[p]);
     }
   }
 }
@@ -479,14 +519,17 @@ __device__ __forceinline__ void half_write(float2* hbuf, int lane, const float2 
   }
 }
 
-// Round HF of a stage's reads: inputs r in [HF R/2, (HF + 1) R/2).
-template <int N, int R, int HF>
+// Round HF of a stage's reads: inputs r in [HF R/2, (HF + 1) R/2), except
+// those in the zero band [R/2 - ZB/2, R/2 + ZB/2) (first stage only), which
+// the codelet treats as zero and which are not read.
+template <int N, int R, int HF, int ZB = 0>
 __device__ __forceinline__ void half_read(const float2* hbuf, int lane, float2 (&v)[(N / R + WAVE - 1) / WAVE][R]) {
   constexpr int NB = N / R;
   constexpr int PER = (NB + WAVE - 1) / WAVE;
   constexpr bool RD_LIN = NB % 16 == 0;
   constexpr int RD_STEP = NB + NB / 16;
   constexpr int PH = pad(N / 2);
+  constexpr int zlo = R / 2 - ZB / 2, zhi = R / 2 + ZB / 2;
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
     const int j = lane + p * WAVE;
@@ -494,24 +537,41 @@ __device__ __forceinline__ void half_read(const float2* hbuf, int lane, float2 (
       if constexpr (RD_LIN) {
         const int b = pad(j);
 #pragma unroll
-        for (int r = HF * R / 2; r < (HF + 1) * R / 2; ++r) v[p][r] = hbuf[b + (r * RD_STEP - HF * PH)];
+        for (int r = HF * R / 2; r < (HF + 1) * R / 2; ++r)
+          if (r < zlo || r >= zhi) v[p][r] = hbuf[b + (r * RD_STEP - HF * PH)];
       } else {
 #pragma unroll
-        for (int r = HF * R / 2; r < (HF + 1) * R / 2; ++r) v[p][r] = hbuf[pad(j + r * NB) - HF * PH];
+        for (int r = HF * R / 2; r < (HF + 1) * R / 2; ++r)
+          if (r < zlo || r >= zhi) v[p][r] = hbuf[pad(j + r * NB) - HF * PH];
       }
     }
   }
 }
 
+// Zero bands of the first stage that the transforms are compiled for: the
+// inputs of a radix-16 first stage at rows [N/2 - ZB N/32, N/2 + ZB N/32)
+// are empty when every nonzero row i satisfies min(i, N - i) < N/2 - ZB N/32.
+// Given that bound (the largest min(i, N - i) + 1 of a nonzero row), the
+// widest band that applies; 0 when none does or the first radix is not 16.
+__host__ __device__ constexpr int zero_band(int n, int bound) {
+  if (pick_radix(n) != 16) return 0;
+  for (int zb = 6; zb > 0; zb -= 2)
+    if (zb != 2 && bound <= n / 2 - zb * (n / 32)) return zb;
+  return 0;
+}
+
+
+
 // The stages from NS on, given the stage's inputs in v; the last stage hands
 // its outputs to emit(ic<QB>, X) as stockham_last_emit does.
-template <int N, int SIGN, int NS, class Emit>
+// ZB: zero band of the first stage's inputs (NS = 1 only; see zero_band).
+template <int N, int SIGN, int NS, int ZB = 0, class Emit>
 __device__ __forceinline__ void half_chain(float2* hbuf, int lane, const float2* __restrict__ tw,
                                            float2 (&v)[(N / pick_radix(N / NS) + WAVE - 1) / WAVE][pick_radix(N / NS)],
                                            Emit&& emit) {
   constexpr int R = pick_radix(N / NS);
   constexpr int PER = (N / R + WAVE - 1) / WAVE;
-  stage_compute<N, R, NS, SIGN>(lane, tw, v);
+  stage_compute<N, R, NS, SIGN, ZB>(lane, tw, v);
   if constexpr (NS * R == N) {
     static_for<0, PER>([&](auto pc) {
       constexpr int p = decltype(pc)::value;
@@ -545,11 +605,13 @@ struct HalfIn {
   float2 v[PER][R];
 };
 
-template <int N, int SIGN, class Emit>
+// ZB: the zero band of the first stage's inputs (see zero_band; the inputs in
+// it need not have been read into `in`), 0 for none.
+template <int N, int SIGN, int ZB = 0, class Emit>
 __device__ __forceinline__ void wave_fft_half_emit(float2* hbuf, int lane, const float2* __restrict__ tw,
                                                    HalfIn<N>& in, Emit&& emit) {
   static_assert(plan_even(N), "half-length exchange needs even radices");
-  half_chain<N, SIGN, 1>(hbuf, lane, tw, in.v, emit);
+  half_chain<N, SIGN, 1, ZB>(hbuf, lane, tw, in.v, emit);
 }
 
 template <int N, int SIGN, int NS = 1>

@@ -271,13 +271,14 @@ struct ImgArgs {
   const double* sd;             // [T][B] sorted geometric delays (metres) or null: no rotation
   const int* n_valid;           // [T]
   const int* n_unflagged;       // [T]
+  const double* vmax;           // [T] largest |v| (metres) of the usable baselines, or null
   int* bnd;                     // [T*C][N + 2]
   int* ncz;                     // [T*C] u-cell columns 0..ncz-1 may be non-empty; the rest are zero
   int ntiles;                   // column tiles per image of the current column kernel
   int* wpart;                   // [T*C][wstride] weight-sum partials, one per column tile
   int* kpart;                   // [T*C][wstride] kept-baseline partials, one per column tile
   int wstride;                  // partial slots per image (>= tiles of any producer kernel)
-  int wtiles;                   // tiles written by the current producer kernel
+  int wtiles;                   // partial slots per image written by the current producer kernel
   int img0, nimg;               // this chunk: images [img0, img0 + nimg)
   float2* half;                 // [chunk][N/2][M] column-transformed half spectrum
   float2* grid;                 // MODE_GRID: [T*C][N][N]
@@ -287,6 +288,7 @@ struct ImgArgs {
   int* n_dropped;               // [T*C] or null
   // adjoint
   const float* image_grad;      // [T*C][M][M]
+  const float* wsum_in;         // [T*C] weight sums of the forward call, or null (count them)
   float2* gamma;                // [chunk][B] gradient w.r.t. V' per image
   float2* vis_grad;             // [T][C][B]
   float2* pacc;                 // [B] sum over images of gamma conj(V)
@@ -342,6 +344,36 @@ __global__ void __launch_bounds__(256) k_bounds(ImgArgs a) {
   if (threadIdx.x == 0) a.ncz[img] = nv == 0 ? 0 : min(H, max(clast, -col(0)) + 1 + reach);
 }
 
+// Largest |v| in metres over the usable baselines of each timestep (one
+// workgroup per timestep). Since x -> rint(x |s|) is non-decreasing, every
+// gridded row of an image at scale s satisfies |i_v| <= rint(vmax |s|), so the
+// rows beyond that bound are known to be empty before the column is gridded.
+__global__ void __launch_bounds__(256) k_vmax(const double* __restrict__ sv, const int* __restrict__ n_valid,
+                                              int B, double* __restrict__ vmax) {
+  __shared__ double red[256];
+  const int t = blockIdx.x;
+  const double* v = sv + (size_t)t * B;
+  const int nv = n_valid[t];
+  double m = 0.0;
+  for (int j = threadIdx.x; j < nv; j += 256) m = fmax(m, fabs(v[j]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) vmax[t] = red[0];
+}
+
+// Zero band of an image's column transforms (see zero_band): the rows beyond
+// rint(vmax |s|) are empty. Non-finite or out-of-range bounds give 0.
+template <int N>
+__device__ __forceinline__ int column_zero_band(const ImgArgs& a, int t, double s) {
+  if (a.vmax == nullptr) return 0;
+  const double vc = rint(a.vmax[t] * fabs(s));
+  return (vc >= 0.0 && vc < (double)(N / 2)) ? zero_band(N, (int)vc + 1) : 0;
+}
+
 // Sum of the per-tile partials of one image (read by one wavefront; every
 // slot below wtiles was written by exactly one workgroup of the producer).
 __device__ __forceinline__ int sum_partials(const int* part, int img, int wstride, int wtiles, int lane) {
@@ -369,6 +401,24 @@ __device__ __forceinline__ float2 baseline_gain(const A& a, int b) {
   const float2 g1 = antenna_gain(a.gains, a.ant1[b], a.n_ant);
   const float2 g2 = antenna_gain(a.gains, a.ant2[b], a.n_ant);
   return cmul(g1, cconj(g2));
+}
+__device__ __forceinline__ float2 load_vis_raw(const ImgArgs& a, size_t off, int ch) {
+  float2 v;
+  if (a.vis_type == VT_C64) {
+    v = static_cast<const float2*>(a.vis)[off];
+  } else if (a.vis_type == VT_F16) {
+    const __half2 h = static_cast<const __half2*>(a.vis)[off];
+    v = __half22float2(h);
+    const float sc = a.vis_scale[ch];
+    v.x *= sc; v.y *= sc;
+  } else {
+    const unsigned int w = static_cast<const unsigned int*>(a.vis)[off];
+    v.x = __uint_as_float(w << 16);
+    v.y = __uint_as_float(w & 0xffff0000u);
+    const float sc = a.vis_scale[ch];
+    v.x *= sc; v.y *= sc;
+  }
+  return v;
 }
 __device__ __forceinline__ float2 load_vis(const ImgArgs& a, size_t off, int b, int ch) {
   float2 v;
@@ -805,7 +855,7 @@ __device__ __forceinline__ int uniform_half(float2* hbuf, const int* hcnt, int l
 // column of at most GU x 64 entries (the usual case) keeps its one step of
 // entries in registers for both halves; longer columns load them again.
 // occ: this lane's occupied cells (uniform weighting).
-template <int N, bool ROT, bool UNI>
+template <int N, bool ROT, bool UNI, int ZB>
 __device__ __forceinline__ void grid_col_half(const ImgArgs& a, const ColSpan& c, float2* hbuf, int* hcnt,
                                               HalfIn<N>& in, int t, int ch, double s, int lane, int& kd,
                                               int& kc, int& occ) {
@@ -836,7 +886,7 @@ __device__ __forceinline__ void grid_col_half(const ImgArgs& a, const ColSpan& c
     occ += uniform_half<N>(hbuf, hcnt, lane);
     wave_sync();
   }
-  half_read<N, R0, 0>(hbuf, lane, in.v);
+  half_read<N, R0, 0, ZB>(hbuf, lane, in.v);
   wave_sync();
   zero_half<N, UNI>(hbuf, hcnt, lane);
   wave_sync();
@@ -855,7 +905,7 @@ __device__ __forceinline__ void grid_col_half(const ImgArgs& a, const ColSpan& c
     occ += uniform_half<N>(hbuf, hcnt, lane);
     wave_sync();
   }
-  half_read<N, R0, 1>(hbuf, lane, in.v);
+  half_read<N, R0, 1, ZB>(hbuf, lane, in.v);
   wave_sync();
 }
 
@@ -863,7 +913,6 @@ __device__ __forceinline__ void grid_col_half(const ImgArgs& a, const ColSpan& c
 template <int N, int CPW, bool UNI>
 __global__ void __launch_bounds__((ColsHalf<N, CPW, UNI>::THREADS)) k_grid_cols_half(ImgArgs a) {
   extern __shared__ float4 lds_raw[];
-  __shared__ int red[2 * CPW];
   using C_ = ColsHalf<N, CPW, UNI>;
   constexpr int H = N / 2;
   const int L = blockIdx.x;
@@ -879,60 +928,60 @@ __global__ void __launch_bounds__((ColsHalf<N, CPW, UNI>::THREADS)) k_grid_cols_
   const int t = img / a.C, ch = img - t * a.C;
   const int c0 = tile * CPW;
   const int ncols = min(H, a.ncz[img]);
+  const int col = c0 + wave;                         // u cell 0..H-1
+  // one weight / kept-baseline partial per column, written by its wavefront
+  int* wslot = a.wpart + (size_t)img * a.wstride + col;
+  int* kslot = a.kpart + (size_t)img * a.wstride + col;
   if (c0 >= ncols) {                                 // the whole tile is empty
-    if (threadIdx.x == 0) {
-      a.wpart[(size_t)img * a.wstride + tile] = 0;
-      a.kpart[(size_t)img * a.wstride + tile] = 0;
-    }
+    if (lane == 0 && col < H) { *wslot = 0; *kslot = 0; }
     return;
   }
-  const int col = c0 + wave;                         // u cell 0..H-1
   const bool active = col < ncols;
   float2* hbuf = lds + wave * C_::STRIDE;
   int* hcnt = UNI ? lcnt + wave * H : nullptr;
   const double s = cells_per_metre(a.freq[ch], a.ndx);
   const float2* tw = stage_twiddles<N>(ltw);
+  // the only workgroup barrier: it publishes the LDS twiddles; after it every
+  // wavefront grids and transforms its column without waiting for the others
+  if (TwLds<N>::ON) __syncthreads();
 
   ColSpan span{0, 0, 0, 0};
   if (active) {
     const int* bnd = a.bnd + (size_t)img * (N + 2);
     span = ColSpan{bnd[col + H], bnd[col + 1 + H], bnd[-col + H], bnd[-col + 1 + H]};
   }
-  HalfIn<N> in;
-  int kd = 0, kc = 0, occ = 0;
-  if (a.sd != nullptr) grid_col_half<N, true, UNI>(a, span, hbuf, hcnt, in, t, ch, s, lane, kd, kc, occ);
-  else grid_col_half<N, false, UNI>(a, span, hbuf, hcnt, in, t, ch, s, lane, kd, kc, occ);
-  // baselines counted once: the direct entry of every cell column, plus the
-  // conjugate entries of columns whose mirror the image path never visits
-  const int kept_b = kd + (col > 0 ? kc : 0);
-  const int mult = col > 0 ? 2 : 1;
-  int wcontrib;
-  if (UNI) {
-    for (int o = WAVE / 2; o > 0; o >>= 1) occ += __shfl_xor(occ, o);
-    wcontrib = mult * occ;
-  } else {
-    wcontrib = mult * (kd + kc);
-  }
-  if (lane == 0) { red[wave] = wcontrib; red[CPW + wave] = kept_b; }
-  __syncthreads();                                   // also publishes the LDS twiddles
-  if (threadIdx.x == 0) {
-    int ws = 0, ks = 0;
-    for (int i = 0; i < CPW; ++i) {
-      ws += red[i];
-      ks += red[CPW + i];
+  // the rest is compiled once per zero band of the first stage and chosen per
+  // workgroup (all of its columns belong to one image)
+  auto body = [&](auto zbc) {
+    constexpr int ZB = decltype(zbc)::value;
+    HalfIn<N> in;
+    int kd = 0, kc = 0, occ = 0;
+    if (a.sd != nullptr) grid_col_half<N, true, UNI, ZB>(a, span, hbuf, hcnt, in, t, ch, s, lane, kd, kc, occ);
+    else grid_col_half<N, false, UNI, ZB>(a, span, hbuf, hcnt, in, t, ch, s, lane, kd, kc, occ);
+    // baselines counted once: the direct entry of every cell column, plus the
+    // conjugate entries of columns whose mirror the image path never visits
+    const int kept_b = kd + (col > 0 ? kc : 0);
+    const int mult = col > 0 ? 2 : 1;
+    int wcontrib;
+    if (UNI) {
+      for (int o = WAVE / 2; o > 0; o >>= 1) occ += __shfl_xor(occ, o);
+      wcontrib = mult * occ;
+    } else {
+      wcontrib = mult * (kd + kc);
     }
-    a.wpart[(size_t)img * a.wstride + tile] = ws;
-    a.kpart[(size_t)img * a.wstride + tile] = ks;
-  }
-  if (active) {
-    // rows of the cutout straight from the last stage: output row m holds
-    // v-frequency q = (m - M/2) mod N
-    float2* dst = a.half + ((size_t)li * H + col) * a.M;
-    const int hm = a.M / 2;
-    wave_fft_half_emit<N, +1>(hbuf, lane, tw, in, [&](auto qb, float2 v) {
-      cutout_block<N, decltype(qb)::value>(lane, hm, [&](unsigned m) { store_at(dst, m, v); });
-    });
-  }
+    if (lane == 0 && col < H) { *wslot = wcontrib; *kslot = kept_b; }
+    if (active) {
+      // rows of the cutout straight from the last stage: output row m holds
+      // v-frequency q = (m - M/2) mod N
+      float2* dst = a.half + ((size_t)li * H + col) * a.M;
+      const int hm = a.M / 2;
+      wave_fft_half_emit<N, +1, ZB>(hbuf, lane, tw, in, [&](auto qb, float2 v) {
+        cutout_block<N, decltype(qb)::value>(lane, hm, [&](unsigned m) { store_at(dst, m, v); });
+      });
+    }
+  };
+  if (HalfIn<N>::R == 16 && column_zero_band<N>(a, t, s) >= 4) body(ic<HalfIn<N>::R == 16 ? 4 : 0>{});
+  else body(ic<0>{});
 }
 
 __global__ void k_grid_finish(ImgArgs a, int n_img) {
@@ -1106,6 +1155,7 @@ __global__ void __launch_bounds__(RowsHalf<N>::THREADS) k_rows_half(ImgArgs a) {
   extern __shared__ float4 lds_raw[];
   constexpr int H = N / 2;
   constexpr int PPW = RowsHalf<N>::PPW;
+  __shared__ int wred[PPW];                          // per-wavefront sums of the weight partials
   constexpr int ST = RowsHalf<N>::STRIDE;
   constexpr int THR = RowsHalf<N>::THREADS;
   constexpr int EPT = (H * PPW + THR - 1) / THR;     // half-spectrum float4 loads per thread
@@ -1131,68 +1181,97 @@ __global__ void __launch_bounds__(RowsHalf<N>::THREADS) k_rows_half(ImgArgs a) {
     const int kt = ln / PPW, pt = ln % PPW;
     const int li = tile / ntr, p0 = (tile % ntr) * PPW;
     const int img = a.img0 + li;
-    const int nz = min(H, a.ncz[img]);
-    float4 ab[EPT];
-    {
-      const float4* src = reinterpret_cast<const float4*>(a.half + (size_t)li * H * M) + (p0 + pt);
+    const int nz = min(H, a.ncz[img]);               // u cells >= nz are empty
+    // the rest of the tile is compiled once per zero band of the first stage
+    // and chosen per tile (all of its rows belong to one image)
+    auto body = [&](auto zbc) {
+      constexpr int ZB = decltype(zbc)::value;
+      float4 ab[EPT];
+      {
+        const float4* src = reinterpret_cast<const float4*>(a.half + (size_t)li * H * M) + (p0 + pt);
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) {
+        for (int i = 0; i < EPT; ++i) {
+          const int k = kt + i * (THR / PPW);
+          ab[i] = (k < nz && p0 + pt < npair) ? src[(size_t)k * (M / 2)] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      }
+      // the image's weight sum W from its partials (integers, or FP32 sums with
+      // a gridding kernel), split over the workgroup and combined in LDS
+      int wli = 0;
+      float wlf = 0.f;
+      for (int i = ln; i < a.wtiles; i += THR) {
+        const int pv = a.wpart[(size_t)img * a.wstride + i];
+        wli += pv;
+        wlf += __int_as_float(pv);
+      }
+      for (int o = WAVE / 2; o > 0; o >>= 1) {
+        if (KB) wlf += __shfl_xor(wlf, o);
+        else wli += __shfl_xor(wli, o);
+      }
+      float2* zs = lds + pt * ST;                       // the packed row this thread fills
+      float2* z = lds + wave * ST;                      // the packed row this wavefront transforms
+      HalfIn<N> in;
+      __syncthreads();                                  // previous tile's rows have left LDS
+      if (lane_i == 0) wred[wave] = KB ? __float_as_int(wlf) : wli;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {                   // lower half: z[k] = A[k] + i B[k]
         const int k = kt + i * (THR / PPW);
-        ab[i] = (k < nz && p0 + pt < npair) ? src[(size_t)k * (M / 2)] : make_float4(0.f, 0.f, 0.f, 0.f);
+        if (k < H) {
+          const float4 v = ab[i];
+          zs[pad(k)] = k == 0 ? make_float2(v.x, v.z) : make_float2(v.x - v.w, v.y + v.z);
+        }
       }
-    }
-    const float W = KB ? sum_partials_f(a.wpart, img, a.wstride, a.wtiles, lane_i)
-                       : (float)sum_partials(a.wpart, img, a.wstride, a.wtiles, lane_i);
-    const float scale = a.norm ? (W > 0 ? 1.0f / W : 0.0f) : 1.0f;
-    if (p0 == 0 && ln == 0 && a.weight_sum) a.weight_sum[img] = W;
-    float2* zs = lds + pt * ST;                       // the packed row this thread fills
-    float2* z = lds + wave * ST;                      // the packed row this wavefront transforms
-    HalfIn<N> in;
-    __syncthreads();                                  // previous tile's rows have left LDS
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {                   // lower half: z[k] = A[k] + i B[k]
-      const int k = kt + i * (THR / PPW);
-      if (k < H) {
-        const float4 v = ab[i];
-        zs[pad(k)] = k == 0 ? make_float2(v.x, v.z) : make_float2(v.x - v.w, v.y + v.z);
-      }
-    }
-    __syncthreads();
-    half_read<N, R0, 0>(z, lane_i, in.v);
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {                   // upper half: z[N - k] = conj A[k] + i conj B[k]
-      const int k = kt + i * (THR / PPW);
-      if (k < H) {
-        const float4 v = ab[i];
-        zs[pad(k == 0 ? 0 : H - k)] = k == 0 ? make_float2(0.f, 0.f) : make_float2(v.x + v.w, v.z - v.y);
-      }
-    }
-    __syncthreads();
-    half_read<N, R0, 1>(z, lane_i, in.v);
-    const int pair = p0 + wave;
-    if (pair < npair) {
-      float* r0 = a.images + ((size_t)img * M + 2 * pair) * M;
-      float* r1 = r0 + M;
-      float s0 = scale, s1 = scale;
+      __syncthreads();
+      float W;
       if (KB) {
-        s0 *= lcorr[2 * pair];
-        s1 *= lcorr[2 * pair + 1];
+        float f = 0.f;
+        for (int w = 0; w < PPW; ++w) f += __int_as_float(wred[w]);
+        W = f;
+      } else {
+        int n = 0;
+        for (int w = 0; w < PPW; ++w) n += wred[w];
+        W = (float)n;
       }
-      int hm = M / 2;
-      asm volatile("" : "+s"(hm));   // block tests stay inside the loop (hoisted they spill)
-      // image columns of the cutout straight from the last stage: column l
-      // holds u-frequency q = (l - M/2) mod N; row 2p is Re z, row 2p+1 is Im z
-      wave_fft_half_emit<N, +1>(z, lane_i, tw, in, [&](auto qb, float2 v) {
-        auto st = [&](unsigned l) {
-          const float cl = KB ? lcorr[l] : 1.0f;
-          store_at(r0, l, v.x * s0 * cl);
-          store_at(r1, l, v.y * s1 * cl);
-        };
-        if constexpr (AL) cutout_block_aligned<N, decltype(qb)::value>(lane_i, hm, st);
-        else cutout_lane<N, decltype(qb)::value>(lane_i, hm, st);
-      });
-    }
+      const float scale = a.norm ? (W > 0 ? 1.0f / W : 0.0f) : 1.0f;
+      if (p0 == 0 && ln == 0 && a.weight_sum) a.weight_sum[img] = W;
+      half_read<N, R0, 0, ZB>(z, lane_i, in.v);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {                   // upper half: z[N - k] = conj A[k] + i conj B[k]
+        const int k = kt + i * (THR / PPW);
+        if (k < H) {
+          const float4 v = ab[i];
+          zs[pad(k == 0 ? 0 : H - k)] = k == 0 ? make_float2(0.f, 0.f) : make_float2(v.x + v.w, v.z - v.y);
+        }
+      }
+      __syncthreads();
+      half_read<N, R0, 1, ZB>(z, lane_i, in.v);
+      const int pair = p0 + wave;
+      if (pair < npair) {
+        float* r0 = a.images + ((size_t)img * M + 2 * pair) * M;
+        float* r1 = r0 + M;
+        float s0 = scale, s1 = scale;
+        if (KB) {
+          s0 *= lcorr[2 * pair];
+          s1 *= lcorr[2 * pair + 1];
+        }
+        int hm = M / 2;
+        asm volatile("" : "+s"(hm));   // block tests stay inside the loop (hoisted they spill)
+        // image columns of the cutout straight from the last stage: column l
+        // holds u-frequency q = (l - M/2) mod N; row 2p is Re z, row 2p+1 is Im z
+        wave_fft_half_emit<N, +1, ZB>(z, lane_i, tw, in, [&](auto qb, float2 v) {
+          auto st = [&](unsigned l) {
+            const float cl = KB ? lcorr[l] : 1.0f;
+            store_at(r0, l, v.x * s0 * cl);
+            store_at(r1, l, v.y * s1 * cl);
+          };
+          if constexpr (AL) cutout_block_aligned<N, decltype(qb)::value>(lane_i, hm, st);
+          else cutout_lane<N, decltype(qb)::value>(lane_i, hm, st);
+        });
+      }
+    };
+    if (HalfIn<N>::R == 16 && zero_band(N, nz) >= 4) body(ic<HalfIn<N>::R == 16 ? 4 : 0>{});
+    else body(ic<0>{});
   }
 }
 
@@ -1582,8 +1661,8 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows_adj(ImgArgs a) {
   const int npair = M / 2;
   const int p0 = blockIdx.x * PPW;
   const int nz = min(H, a.ncz[img]);
-  const int W = sum_partials(a.wpart, img, a.wstride, a.wtiles, lane);
-  const float scale = a.norm ? (W > 0 ? 1.0f / (float)W : 0.0f) : 1.0f;
+  const float W = a.wsum_in ? a.wsum_in[img] : (float)sum_partials(a.wpart, img, a.wstride, a.wtiles, lane);
+  const float scale = a.norm ? (W > 0 ? 1.0f / W : 0.0f) : 1.0f;
   const float2* tw = stage_twiddles<N>(lds + PPW * ST);
   __syncthreads();
   const int pair = p0 + wave;
@@ -1709,9 +1788,12 @@ __global__ void __launch_bounds__(Cols<N>::THREADS) k_cols_adj(ImgArgs a) {
           g = cconj(w);
         }
         const int b = a.perm[tb + j];
+        // gradient with respect to V' = g1 conj(g2) V: the load multiplied V' by
+        // exp(+2 pi i d nu / c) (rotation, cables), so its gradient carries the conjugate
+        if (a.sd != nullptr) g = rotate_phase(g, -a.sd[tb + j], a.freq[ch]);
         if (a.gains) {
           a.vis_grad[vb + b] = cmul(cconj(baseline_gain(a, b)), g);
-          const float2 v = static_cast<const float2*>(a.vis)[vb + b];
+          const float2 v = load_vis_raw(a, vb + b, ch);
           a.gamma[(size_t)li * a.B + b] = cmul(g, cconj(v));
         } else {
           a.vis_grad[vb + b] = g;

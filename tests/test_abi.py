@@ -141,12 +141,16 @@ def test_grid_and_adjoint_validation(lib):
     assert g(ctypes.byref(_prob(grid_n=7)), ctypes.byref(inp), FAKE, None, None, None, None, 0,
              None) == E_SIZE
     a = lib.blink_degrid_adjoint
-    # the adjoint is built for complex64 visibilities only
-    assert a(ctypes.byref(_prob(vis_type=1)), ctypes.byref(_inputs(vis_scale=FAKE)), FAKE, FAKE,
-             None, None, 0, None) == E_UNSUP
+    # FP16 storage passes validation (and then needs a workspace); without its scale it is refused
+    assert a(ctypes.byref(_prob(vis_type=1)), ctypes.byref(_inputs(vis_scale=FAKE)), FAKE, None, FAKE,
+             None, None, 0, None) == E_WS
+    assert a(ctypes.byref(_prob(vis_type=1)), ctypes.byref(inp), FAKE, None, FAKE, None, None, 0,
+             None) == E_ARG
     # a gain gradient needs gains
-    assert a(ctypes.byref(p), ctypes.byref(inp), FAKE, FAKE, FAKE, None, 0, None) == E_ARG
-    assert a(ctypes.byref(p), ctypes.byref(inp), None, FAKE, None, None, 0, None) == E_ARG
+    assert a(ctypes.byref(p), ctypes.byref(inp), FAKE, None, FAKE, FAKE, None, 0, None) == E_ARG
+    assert a(ctypes.byref(p), ctypes.byref(inp), None, None, FAKE, None, None, 0, None) == E_ARG
+    # the forward weight sums are optional
+    assert a(ctypes.byref(p), ctypes.byref(inp), FAKE, FAKE, FAKE, None, None, 0, None) == E_WS
 
 
 def test_workspace_sizes_scale(lib):
@@ -167,10 +171,10 @@ def test_workspace_sizes_scale(lib):
 def test_kernel_gridding_has_no_adjoint(lib):
     p = _prob(kernel_support=6, kernel_beta=-1.0)
     a = lib.blink_degrid_adjoint
-    assert a(ctypes.byref(p), ctypes.byref(_inputs()), FAKE, FAKE, None, None, 0, None) == E_UNSUP
+    assert a(ctypes.byref(p), ctypes.byref(_inputs()), FAKE, None, FAKE, None, None, 0, None) == E_UNSUP
     # the same problem without the kernel passes validation (and then needs a workspace)
     p0 = _prob()
-    assert a(ctypes.byref(p0), ctypes.byref(_inputs()), FAKE, FAKE, None, None, 0, None) == E_WS
+    assert a(ctypes.byref(p0), ctypes.byref(_inputs()), FAKE, None, FAKE, None, None, 0, None) == E_WS
 
 
 def test_dynamic_spectra_validation(lib):
@@ -198,21 +202,23 @@ def test_correlate_validation(lib):
     assert c(None, 0, 4, 8, 32, None, None, None) == E_OK                # empty
 
 
-def test_phase_rotation_has_no_adjoint(lib):
+def test_phase_rotation_adjoint_passes_validation(lib):
+    # a rotated problem's adjoint is built: it passes validation and then needs a workspace
     p = _prob(phase_l=0.1, phase_m=-0.2)
     a = lib.blink_degrid_adjoint
-    assert a(ctypes.byref(p), ctypes.byref(_inputs()), FAKE, FAKE, None, None, 0, None) == E_UNSUP
+    assert a(ctypes.byref(p), ctypes.byref(_inputs()), FAKE, None, FAKE, None, None, 0, None) == E_WS
+    assert lib.blink_workspace_size(ctypes.byref(p), 2) > 0
 
 
 def test_workspace_holds_the_delay_table(lib):
-    # image and grid calls reserve the [T][B] delay table of the phase rotation
+    # image, grid and adjoint calls reserve the [T][B] delay table of the phase rotation
     # and the cable correction whether or not one is applied (cable lengths are
     # an input, which the size query does not see); with the two sort key
     # buffers, two index buffers, sorted u, v and order that is 52 B per
     # baseline and timestep
     p0 = _prob(n_bl=1000)
     p1 = _prob(n_bl=1000, phase_l=0.1)
-    for call in (0, 1):
+    for call in (0, 1, 2):
         s0 = lib.blink_workspace_size(ctypes.byref(p0), call)
         assert s0 == lib.blink_workspace_size(ctypes.byref(p1), call)
         assert s0 >= 2 * 1000 * 52
@@ -225,7 +231,9 @@ def test_cable_correction_validation(lib):
     assert _image(lib, _prob(n_ant=0), _inputs(cable_m=FAKE, ant1=FAKE, ant2=FAKE)) == E_ARG
     a = lib.blink_degrid_adjoint
     inp = _inputs(cable_m=FAKE, ant1=FAKE, ant2=FAKE)
-    assert a(ctypes.byref(_prob()), ctypes.byref(inp), FAKE, FAKE, None, None, 0, None) == E_UNSUP
+    assert a(ctypes.byref(_prob()), ctypes.byref(inp), FAKE, None, FAKE, None, None, 0, None) == E_WS
+    assert a(ctypes.byref(_prob()), ctypes.byref(_inputs(cable_m=FAKE)), FAKE, None, FAKE, None, None, 0,
+             None) == E_ARG
 
 
 def _noalloc(lib, p, inp, images=FAKE):

@@ -99,3 +99,122 @@ def test_autograd_matches_oracle_gradient():
     eg = rel_l2(gains.grad.cpu().numpy().view(np.float32), rg.view(np.float64))
     print(f"  autograd vs oracle: vis {ev:.2e} gains {eg:.2e}", flush=True)
     assert ev <= 1e-5 and eg <= 1e-5
+
+
+def _rot_inputs(w, d, seed):
+    rng = np.random.default_rng(seed)
+    cab = rng.uniform(0.0, 300.0, w.n_ant)
+    d = dict(d, cable_m=torch.from_numpy(cab).to(device()), ant1=torch.from_numpy(w.ant1).to(device()),
+             ant2=torch.from_numpy(w.ant2).to(device()))
+    return cab, d
+
+
+@pytest.mark.parametrize("name", ["wide1024_gains", "subset64_gains", "allsky180_uniform"])
+def test_adjoint_with_rotation_and_cables_vs_oracle(name):
+    """The adjoint applies the conjugate of the rotation / cable factor: vis and
+    gain gradients match the oracle's rotated adjoint (Sec. 4.2 (i), (iii))."""
+    from oracle import phase_rotation as pr
+    w, use_g = _case(name)
+    d = inputs(w, with_gains=use_g)
+    lm = (0.04, -0.03)
+    cab, d = _rot_inputs(w, d, 11)
+    rng = np.random.default_rng(23)
+    gbar = torch.from_numpy(rng.normal(size=(w.n_img, w.out_n, w.out_n)).astype(np.float32)).to(device())
+    g = d.get("gains")
+    vg, gg = blink.degrid_adjoint(gbar, d["vis"], d["uvw_m"], d["freq_hz"], grid_n=w.grid_n,
+                                  pixscale=w.pixscale, out_n=w.out_n, weighting=w.weighting, norm=w.norm,
+                                  flags=d["flags"], gains=g, ant1=d["ant1"], ant2=d["ant2"],
+                                  phase_lm=lm, cable_m=d["cable_m"])
+    torch.cuda.synchronize()
+    rv, rg = pr.adjoint_batch_rotated(gbar.cpu().numpy().astype(np.float64), d["vis"].cpu().numpy(), w.uvw_m,
+                                      w.freq_hz, w.grid_n, w.pixscale, w.weighting, w.norm, lm[0], lm[1],
+                                      w.flags, w.gains if use_g else None, w.ant1, w.ant2, cable_m=cab)
+    e = rel_l2(vg.cpu().numpy().view(np.float32), rv.view(np.float64))
+    print(f"  rotated vis_grad rel-L2 {e:.2e}", flush=True)
+    assert e <= 1e-5
+    if use_g:
+        eg = rel_l2(gg.cpu().numpy().view(np.float32), rg.view(np.float64))
+        print(f"  rotated gain_grad rel-L2 {eg:.2e}", flush=True)
+        assert eg <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["wide1024_gains", "allsky180_uniform"])
+def test_adjoint_reuses_forward_weight_sums(name):
+    """With the forward call's weight sums the adjoint skips counting them and
+    gives the same bits."""
+    w, use_g = _case(name)
+    d = inputs(w, with_gains=use_g)
+    _, wsum = run_image_w(w, d)
+    rng = np.random.default_rng(5)
+    gbar = torch.from_numpy(rng.normal(size=(w.n_img, w.out_n, w.out_n)).astype(np.float32)).to(device())
+    kw = dict(grid_n=w.grid_n, pixscale=w.pixscale, out_n=w.out_n, weighting=w.weighting, norm=w.norm,
+              flags=d["flags"], gains=d.get("gains"), ant1=d.get("ant1"), ant2=d.get("ant2"))
+    a = blink.degrid_adjoint(gbar, d["vis"], d["uvw_m"], d["freq_hz"], **kw)
+    b = blink.degrid_adjoint(gbar, d["vis"], d["uvw_m"], d["freq_hz"], weight_sum=wsum, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0])
+    if use_g:
+        assert torch.equal(a[1], b[1])
+
+
+def run_image_w(w, d):
+    ws = torch.empty(w.n_img, dtype=torch.float32, device=device())
+    img = blink.image_batch(d["vis"], d["uvw_m"], d["freq_hz"], grid_n=w.grid_n, pixscale=w.pixscale,
+                            out_n=w.out_n, weighting=w.weighting, norm=w.norm, flags=d.get("flags"),
+                            gains=d.get("gains"), ant1=d.get("ant1"), ant2=d.get("ant2"), weight_sum=ws)
+    return img, ws
+
+
+@pytest.mark.parametrize("dt", [torch.float16, torch.bfloat16])
+def test_adjoint_half_storage_vs_oracle(dt):
+    """FP16/BF16 storage: the gradient with respect to the dequantised
+    visibilities (and the gains) matches the oracle's adjoint on those values."""
+    w, _ = _case("wide1024_gains")
+    d = inputs(w, with_gains=True)
+    q, sig = synth.quantize_vis(d["vis"], dt)
+    rng = np.random.default_rng(29)
+    gbar = torch.from_numpy(rng.normal(size=(w.n_img, w.out_n, w.out_n)).astype(np.float32)).to(device())
+    vg, gg = blink.degrid_adjoint(gbar, q, d["uvw_m"], d["freq_hz"], grid_n=w.grid_n, pixscale=w.pixscale,
+                                  out_n=w.out_n, weighting=w.weighting, norm=w.norm, gains=d["gains"],
+                                  ant1=d["ant1"], ant2=d["ant2"], vis_scale=sig)
+    torch.cuda.synchronize()
+    qn = q.cpu()
+    if dt == torch.bfloat16:
+        bits = qn.view(torch.int16).numpy().view(np.uint16)
+        re, im = bits[..., 0], bits[..., 1]
+    else:
+        re, im = qn[..., 0].numpy(), qn[..., 1].numpy()
+    deq = oracle.dequantize(re, im, sig.cpu().numpy()[None, :, None].astype(np.float64))
+    rv, rg = oracle.adjoint_batch(gbar.cpu().numpy().astype(np.float64), deq, w.uvw_m, w.freq_hz, w.grid_n,
+                                  w.pixscale, w.weighting, w.norm, None, w.gains, w.ant1, w.ant2)
+    e = rel_l2(vg.cpu().numpy().view(np.float32), rv.view(np.float64))
+    eg = rel_l2(gg.cpu().numpy().view(np.float32), rg.view(np.float64))
+    print(f"  {dt}: vis_grad {e:.2e} gain_grad {eg:.2e}", flush=True)
+    assert e <= 1e-5 and eg <= 1e-5
+
+
+def test_autograd_with_rotation_and_cables():
+    from oracle import phase_rotation as pr
+    w, _ = _case("subset64_gains")
+    d = inputs(w, with_gains=True)
+    lm = (0.02, 0.05)
+    cab, d = _rot_inputs(w, d, 13)
+    vis = d["vis"].clone().requires_grad_(True)
+    gains = d["gains"].clone().requires_grad_(True)
+    rng = np.random.default_rng(9)
+    target = torch.from_numpy(rng.normal(size=(w.n_img, w.out_n, w.out_n)).astype(np.float32)).to(device())
+    img = blink.blink_image(vis, gains, d["uvw_m"], d["freq_hz"], d["ant1"], d["ant2"], grid_n=w.grid_n,
+                            pixscale=w.pixscale, out_n=w.out_n, weighting=w.weighting, norm=w.norm,
+                            phase_lm=lm, cable_m=d["cable_m"])
+    ((img - target) ** 2).sum().backward()
+    vnp = d["vis"].cpu().numpy()
+    ref, _ = pr.image_batch_rotated(vnp, w.uvw_m, w.freq_hz, w.grid_n, w.pixscale, w.out_n, w.weighting,
+                                    w.norm, lm[0], lm[1], gains=w.gains, ant1=w.ant1, ant2=w.ant2, cable_m=cab)
+    assert rel_l2(img.detach().cpu().numpy(), ref) <= 1e-5
+    rv, rg = pr.adjoint_batch_rotated(2 * (ref - target.cpu().numpy()), vnp, w.uvw_m, w.freq_hz, w.grid_n,
+                                      w.pixscale, w.weighting, w.norm, lm[0], lm[1], gains=w.gains,
+                                      ant1=w.ant1, ant2=w.ant2, cable_m=cab)
+    ev = rel_l2(vis.grad.cpu().numpy().view(np.float32), rv.view(np.float64))
+    eg = rel_l2(gains.grad.cpu().numpy().view(np.float32), rg.view(np.float64))
+    print(f"  rotated autograd vs oracle: vis {ev:.2e} gains {eg:.2e}", flush=True)
+    assert ev <= 1e-5 and eg <= 1e-5

@@ -328,3 +328,42 @@ def test_origin_baseline_lands_in_column_zero():
     r = oracle.image_one(vis[0, 0], uv[:, 0], uv[:, 1], w.freq_hz[0], 8, w.pixscale, 8, 0, 1)
     assert np.array_equal(cnt[0], r["counts"])
     assert rel_l2(img[0], r["image"]) <= REL_L2_FP32
+
+
+# ------------------------------------------------------------------ zero band of the first stage
+def _engineered(n_bl, grid_n, umax_cell, vmax_cell, seed):
+    """A one-image problem with exactly one cell per metre (N dx nu = c) whose
+    gridded cells reach |i_u| = umax_cell and |i_v| = vmax_cell and no further."""
+    rng = np.random.default_rng(seed)
+    C = oracle.C_LIGHT
+    dx = 1.0 / grid_n                     # N dx = 1, nu = c -> s = 1 cell per metre
+    u = rng.integers(-umax_cell, umax_cell + 1, n_bl).astype(np.float64) + rng.uniform(-0.45, 0.45, n_bl)
+    v = rng.integers(-vmax_cell, vmax_cell + 1, n_bl).astype(np.float64) + rng.uniform(-0.45, 0.45, n_bl)
+    u[0], v[0] = float(umax_cell), -float(vmax_cell)     # the extreme cells are occupied
+    u[1], v[1] = -float(umax_cell) + 0.3, float(vmax_cell) - 0.2
+    np.clip(u, -umax_cell - 0.49, umax_cell + 0.49, out=u)
+    np.clip(v, -vmax_cell - 0.49, vmax_cell + 0.49, out=v)
+    uvw = np.zeros((1, n_bl, 3))
+    uvw[0, :, 0], uvw[0, :, 1] = u, v
+    vis = (rng.normal(size=(1, 1, n_bl)) + 1j * rng.normal(size=(1, 1, n_bl))).astype(np.complex64)
+    return uvw, np.array([C]), dx, vis
+
+
+@pytest.mark.parametrize("umax,vmax", [(319, 319), (320, 320), (383, 383), (384, 384), (319, 383), (383, 100),
+                                       (100, 511), (511, 0)])
+def test_first_stage_zero_band_edges(umax, vmax):
+    """The first radix-16 stage skips its middle inputs when the rows (column
+    pass: |i_v| <= rint(vmax s)) or u cells (row pass: below ncz) cannot reach
+    them: 6 of 16 inputs for a bound <= 320 at N = 1024, 4 for <= 384. Cells
+    right at and one past each bound match the oracle."""
+    n, m = 1024, 512
+    print(f"\n[gpu] zero band: max |i_u| {umax}, max |i_v| {vmax}", flush=True)
+    uvw, freq, dx, vis = _engineered(400, n, umax, vmax, seed=umax * 1000 + vmax)
+    dev = device()
+    img = blink.image_batch(torch.from_numpy(vis).to(dev), torch.from_numpy(uvw).to(dev),
+                            torch.from_numpy(freq).to(dev), grid_n=n, pixscale=dx, out_n=m,
+                            weighting=0, norm=1)
+    ref, _ = oracle.image_batch(vis, uvw, freq, n, dx, m, 0, 1)
+    iu, iv, keep = oracle.cell_index(uvw[0, :, 0], uvw[0, :, 1], 1.0, n)
+    assert np.abs(iu[keep]).max() == umax and np.abs(iv[keep]).max() == vmax
+    assert rel_l2(img.cpu().numpy()[0], ref[0]) <= REL_L2_FP32

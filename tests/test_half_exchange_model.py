@@ -147,3 +147,43 @@ def test_rounds_split_at_half_for_every_stage():
                 base = (j // ns) * ns * r + j % ns
                 lows = [base + rr * ns < n // 2 for rr in range(r)]
                 assert all(lows) if j < nb // 2 else not any(lows)
+
+
+# ---------------------------------------------------------------- zero band
+def zero_band(n, bound):
+    """The rule the kernels use: the widest of 6, 4 middle inputs of a radix-16
+    first stage that every nonzero row (min(i, n - i) < bound) avoids."""
+    if pick_radix(n) != 16:
+        return 0
+    for zb in (6, 4):
+        if bound <= n // 2 - zb * (n // 32):
+            return zb
+    return 0
+
+
+@pytest.mark.parametrize("n", [32, 64, 128, 256, 512, 1024, 2048])
+def test_zero_band_inputs_are_empty_rows(n):
+    """A radix-16 first stage reads x[j + r n/16] for butterfly j < n/16; the
+    band r in [8 - zb/2, 8 + zb/2) covers rows [n/2 - zb n/32, n/2 + zb n/32).
+    For every bound, those rows hold no row with min(i, n - i) < bound, so
+    skipping those inputs leaves every butterfly's result unchanged; the
+    transform with the band zeroed equals the full one."""
+    rng = np.random.default_rng(n)
+    nb = n // 16
+    for bound in range(0, n // 2 + 2):
+        zb = zero_band(n, bound)
+        if zb == 0:
+            continue
+        rows = [j + r * nb for j in range(nb) for r in range(8 - zb // 2, 8 + zb // 2)]
+        assert min(rows) == n // 2 - zb * n // 32 and max(rows) == n // 2 + zb * n // 32 - 1
+        assert all(min(i, n - i) >= bound for i in rows)
+    # a column whose rows reach exactly the bound: the band's inputs are zero
+    for bound, zb in ((n // 2 - 6 * n // 32, 6), (n // 2 - 4 * n // 32, 4)):
+        assert zero_band(n, bound) == zb and zero_band(n, bound + 1) < zb
+        x = np.zeros(n, complex)
+        i = np.arange(n)
+        live = np.minimum(i, n - i) < bound
+        x[live] = rng.normal(size=live.sum()) + 1j * rng.normal(size=live.sum())
+        band = np.zeros(n, bool)
+        band[n // 2 - zb * n // 32: n // 2 + zb * n // 32] = True
+        assert not np.any(live & band)

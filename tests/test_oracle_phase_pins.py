@@ -124,3 +124,64 @@ def test_cable_lengths_of_a_tilted_plane_equal_the_geometric_rotation():
     by_cable = pr.rotate(v, uvw, freq, 0.0, 0.0, cab, a1, a2)
     by_geometry = pr.rotate(v, uvw, freq, l0, m0)
     assert np.allclose(by_cable, by_geometry, rtol=0, atol=1e-12)
+
+
+def _rot_case(seed=31, n=16, nb=36, n_ant=9):
+    rng = np.random.default_rng(seed)
+    uvw = np.zeros((1, nb, 3))
+    uvw[0, :, 0] = rng.uniform(-6, 6, nb)
+    uvw[0, :, 1] = rng.uniform(-6, 6, nb)
+    uvw[0, :, 2] = rng.uniform(-2, 2, nb)
+    a1 = rng.integers(0, n_ant, nb)
+    a2 = (a1 + 1 + rng.integers(0, n_ant - 1, nb)) % n_ant
+    vis = (rng.normal(size=(1, 1, nb)) + 1j * rng.normal(size=(1, 1, nb)))
+    g = 1 + 0.05 * rng.normal(size=n_ant) + 0.05j * rng.normal(size=n_ant)
+    cab = rng.uniform(0, 40, n_ant)
+    return uvw, vis, a1, a2, g, cab, np.array([oracle.C_LIGHT]), 1.0 / n
+
+
+def test_rotated_adjoint_dot_product():
+    # gains off: the rotated image is linear in V, so <I(V), Ibar> = sum Re(conj(grad) V)
+    uvw, vis, a1, a2, g, cab, freq, dx = _rot_case()
+    rng = np.random.default_rng(4)
+    ibar = rng.normal(size=(1, 12, 12))
+    img, _ = pr.image_batch_rotated(vis, uvw, freq, 16, dx, 12, 0, 1, 0.2, -0.1, cable_m=cab, ant1=a1,
+                                    ant2=a2)
+    vg, _ = pr.adjoint_batch_rotated(ibar, vis, uvw, freq, 16, dx, 0, 1, 0.2, -0.1, cable_m=cab,
+                                     ant1=a1, ant2=a2)
+    lhs = np.sum(img * ibar)
+    rhs = np.sum(vg.real * vis.real + vg.imag * vis.imag)
+    assert np.isclose(lhs, rhs, rtol=1e-12, atol=1e-12)
+
+
+def test_rotated_adjoint_finite_differences():
+    # FP64 central differences of ||I - T||^2 through rotation, cable lengths and gains
+    uvw, vis, a1, a2, g, cab, freq, dx = _rot_case(seed=32)
+    rng = np.random.default_rng(6)
+    target = rng.normal(size=(1, 14, 14))
+    kw = dict(cable_m=cab, ant1=a1, ant2=a2)
+
+    def loss(vv, gg):
+        img, _ = pr.image_batch_rotated(vv, uvw, freq, 16, dx, 14, 1, 1, 0.15, 0.1, gains=gg, **kw)
+        return float(np.sum((img - target) ** 2))
+
+    img, _ = pr.image_batch_rotated(vis, uvw, freq, 16, dx, 14, 1, 1, 0.15, 0.1, gains=g, **kw)
+    vg, gg = pr.adjoint_batch_rotated(2 * (img - target), vis, uvw, freq, 16, dx, 1, 1, 0.15, 0.1,
+                                      gains=g, **kw)
+
+    def fd(f, x, idx, part):
+        h = 1e-6 * max(1.0, abs(x[idx]))
+        xp = x.copy(); xp[idx] += h if part == 0 else 1j * h
+        xm = x.copy(); xm[idx] -= h if part == 0 else 1j * h
+        return (f(xp) - f(xm)) / (2 * h)
+
+    for k in range(len(g)):
+        for part in (0, 1):
+            num = fd(lambda q: loss(vis, q), g, k, part)
+            ana = (gg[k].real, gg[k].imag)[part]
+            assert abs(num - ana) <= 1e-6 * max(1.0, abs(ana))
+    for b in range(0, vis.shape[2], 2):
+        for part in (0, 1):
+            num = fd(lambda q: loss(q, g), vis, (0, 0, b), part)
+            ana = (vg[0, 0, b].real, vg[0, 0, b].imag)[part]
+            assert abs(num - ana) <= 1e-6 * max(1.0, abs(ana))
