@@ -446,7 +446,38 @@ def bench_images(args, np, torch, blink, synth, dev):
     }
     out.update(extra)
     if args.workload == "plain":
+        # the instrumented call above waits on an event pair around every launch;
+        # the plain path's own costs: back-to-back calls (the host enqueues the
+        # next while the GPU runs) and one call waited for on its own
+        one = torch.empty((1, M, M), dtype=torch.float32, device=dev)
+        p1 = blink.blink.make_problem(vis, uvw, freq, N, w.pixscale, M, w.weighting, w.norm)
+        ws1 = blink.workspace(p1, blink.CALL_IMAGE, dev)
+
+        def call():
+            blink.image_batch(vis, uvw, freq, grid_n=N, pixscale=w.pixscale, out_n=M, weighting=w.weighting,
+                              norm=w.norm, images=one, ws=ws1)
+        for _ in range(20):
+            call()
+        torch.cuda.synchronize()
+        nl = 500
+        t0 = time.perf_counter()
+        for _ in range(nl):
+            call()
+        torch.cuda.synchronize()
+        loop_us = (time.perf_counter() - t0) / nl * 1e6
+        lat = []
+        for _ in range(200):
+            t0 = time.perf_counter()
+            call()
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0)
+        lat.sort()
         out["latency_us_per_image"] = round(res["ms_per_step"] * 1e3, 2)
+        out["back_to_back_us_per_call"] = round(loop_us, 2)
+        out["single_call_latency_us_median"] = round(lat[len(lat) // 2] * 1e6, 2)
+        out["latency_note"] = ("latency_us_per_image times the instrumented entry point (an event pair and a "
+                               "host wait around every launch); back_to_back_us_per_call is the plain "
+                               "call in a loop, single_call_latency_us_median one call and a synchronisation")
 
     sample_n = args.cpu_sample if args.cpu_sample is not None else {"widefield": 128, "widefield_kb": 32, "widefield_rot": 0, "plain": 64, "allsky": 4096, "precision": 16}[args.workload]
     if not args.no_cpu_baseline and sample_n > 0:
@@ -507,6 +538,24 @@ def bench_diff(args, np, torch, blink, synth, dev):
     fw1.record()
     torch.cuda.synchronize()
     fwd_ms = fw0.elapsed_time(fw1) / args.steps
+    # the library's adjoint alone (degridding + forward transforms + gain
+    # gradient, reusing the forward weight sums), for the backward / forward ratio
+    img0 = blink.image_batch(vis0, uvw, freq, grid_n=w.grid_n, pixscale=w.pixscale, out_n=w.out_n,
+                             weighting=w.weighting, norm=w.norm, gains=gains0, ant1=a1, ant2=a2)
+    wsum = torch.empty(w.n_img, dtype=torch.float32, device=dev)
+    blink.image_batch(vis0, uvw, freq, grid_n=w.grid_n, pixscale=w.pixscale, out_n=w.out_n,
+                      weighting=w.weighting, norm=w.norm, gains=gains0, ant1=a1, ant2=a2, weight_sum=wsum)
+    gbar = (2 * (img0 - target)).contiguous()
+    torch.cuda.synchronize()
+    ad0, ad1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ad0.record()
+    for _ in range(args.steps):
+        blink.degrid_adjoint(gbar, vis0, uvw, freq, grid_n=w.grid_n, pixscale=w.pixscale, out_n=w.out_n,
+                             weighting=w.weighting, norm=w.norm, gains=gains0, ant1=a1, ant2=a2,
+                             weight_sum=wsum)
+    ad1.record()
+    torch.cuda.synchronize()
+    adj_ms = ad0.elapsed_time(ad1) / args.steps
     out = {"metric": "dirty images/s forward + backward (diff)", "value": round(w.n_img / (ms / 1e3), 1),
            "unit": "images/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -514,6 +563,11 @@ def bench_diff(args, np, torch, blink, synth, dev):
            "config": {"workload": DESCRIPTION["diff"], "images_per_step": w.n_img, "grid_n": w.grid_n,
                       "out_n": w.out_n, "baselines": w.n_bl, "antennas": w.n_ant},
            "forward_ms_per_step": round(fwd_ms, 4), "backward_ms_per_step": round(ms - fwd_ms, 4),
+           "adjoint_call_ms_per_step": round(adj_ms, 4),
+           "adjoint_over_forward": round(adj_ms / fwd_ms, 3),
+           "backward_note": "backward_ms_per_step is the autograd step (torch's loss-gradient kernels "
+                            "over the 320 images plus the adjoint call); adjoint_call_ms_per_step times "
+                            "blink_degrid_adjoint alone",
            "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 

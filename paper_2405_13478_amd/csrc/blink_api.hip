@@ -238,9 +238,15 @@ struct Timer {
   }
 };
 
-// per-timestep order of the usable baselines by u (metres)
-void run_sort(const blink_problem* p, const blink_inputs* in, const Work& w, hipStream_t st,
-              Timer* tm = nullptr) {
+// What run_sort produced beside the sorted lists.
+constexpr int SORTED_VMAX = 1;     // the per-timestep largest |v|
+constexpr int SORTED_BOUNDS = 2;   // the cell bounds of every image (one channel per timestep)
+
+// per-timestep order of the usable baselines by u (metres). With `img` (the
+// image call), the small-list sort also writes the per-timestep largest |v|
+// and, when there is one channel per timestep, the images' cell bounds.
+int run_sort(const blink_problem* p, const blink_inputs* in, const Work& w, hipStream_t st,
+             Timer* tm = nullptr, bool img = false) {
   Timer none;
   Timer& T_ = tm ? *tm : none;
   const int T = p->n_time, B = p->n_bl;
@@ -261,23 +267,36 @@ void run_sort(const blink_problem* p, const blink_inputs* in, const Work& w, hip
     s.ant2 = in->ant2;
     s.n_ant = p->n_ant;
   }
+  const bool small = B > 0 && B <= SORT_RUN;
+  const bool bounds = img && small && p->n_chan == 1;
+  if (img && small) s.vmax = w.vmax;
+  if (bounds) {
+    s.N = p->grid_n;
+    s.kw = p->kernel_support;
+    s.ndx = (double)p->grid_n * p->pixscale;
+    s.freq = in->freq_hz;
+    s.bnd = w.bnd;
+    s.ncz = w.ncz;
+  }
   if (B == 0 || B > SORT_RUN) {
     T_.begin(0);
     hipLaunchKernelGGL(k_sort_init, dim3(cdiv(2LL * T, 256)), dim3(256), 0, st, w.counters, 2 * T);
     T_.end();
   }
-  if (B == 0 || T == 0) return;
+  if (B == 0 || T == 0) return 0;
   for (int t0 = 0; t0 < T; t0 += MAX_GRID_Y) {
     const int nt = std::min(MAX_GRID_Y, T - t0);
     s.t0 = t0;
     T_.begin(0);
     if (B <= SORT_RUN_SMALL) {
-      hipLaunchKernelGGL((k_sort_small<SORT_RUN_SMALL>), dim3(1, nt), dim3(1024), 0, st, s);
+      if (bounds) hipLaunchKernelGGL((k_sort_small<SORT_RUN_SMALL, true>), dim3(1, nt), dim3(1024), 0, st, s);
+      else hipLaunchKernelGGL((k_sort_small<SORT_RUN_SMALL>), dim3(1, nt), dim3(1024), 0, st, s);
       T_.end();
       continue;
     }
     if (B <= SORT_RUN) {
-      hipLaunchKernelGGL((k_sort_small<SORT_RUN>), dim3(1, nt), dim3(1024), 0, st, s);
+      if (bounds) hipLaunchKernelGGL((k_sort_small<SORT_RUN, true>), dim3(1, nt), dim3(1024), 0, st, s);
+      else hipLaunchKernelGGL((k_sort_small<SORT_RUN>), dim3(1, nt), dim3(1024), 0, st, s);
       T_.end();
       continue;
     }
@@ -294,6 +313,7 @@ void run_sort(const blink_problem* p, const blink_inputs* in, const Work& w, hip
     hipLaunchKernelGGL(k_sort_finish, dim3(cdiv(B, 256), nt), dim3(256), 0, st, s, src);
     T_.end();
   }
+  return small && img ? (SORTED_VMAX | (bounds ? SORTED_BOUNDS : 0)) : 0;
 }
 
 ImgArgs make_args(const blink_problem* p, const blink_inputs* in, const Work& w) {
@@ -405,7 +425,7 @@ void launch_rows(const blink_problem* p, ImgArgs& a, long long nwg, size_t lds, 
 }
 
 template <int N>
-blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t st, Timer* tm) {
+blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t st, Timer* tm, int sorted) {
   Timer& T_ = *tm;
   const long long n_img = (long long)p->n_time * p->n_chan;
   const bool uni = p->weighting == BLINK_UNIFORM;
@@ -417,9 +437,11 @@ blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t s
   if (rows_lds > LDS_PER_CU) return BLINK_E_UNSUPPORTED;
   // partials per image: one per column (half-length column kernel) or per tile
   a.wtiles = cols_half<N>() && !kb ? N / 2 : (int)cdiv(N / 2, cpw);
-  T_.begin(1);
-  hipLaunchKernelGGL(k_bounds, dim3((unsigned)n_img), dim3(256), 0, st, a);
-  T_.end();
+  if (!(sorted & SORTED_BOUNDS)) {
+    T_.begin(1);
+    hipLaunchKernelGGL(k_bounds, dim3((unsigned)n_img), dim3(256), 0, st, a);
+    T_.end();
+  }
   for (long long i0 = 0; i0 < n_img; i0 += chunk) {
     const int n = (int)std::min<long long>(chunk, n_img - i0);
     a.img0 = (int)i0; a.nimg = n;
@@ -637,8 +659,8 @@ static blink_status image_batch_impl(const blink_problem* p, const blink_inputs*
   tm->st = st;
   Work w{};
   carve(p, BLINK_CALL_IMAGE, chunk, static_cast<char*>(workspace), &w);
-  run_sort(p, in, w, st, tm);
-  if (p->n_bl > 0) {
+  const int sorted = run_sort(p, in, w, st, tm, true);
+  if (p->n_bl > 0 && !(sorted & SORTED_VMAX)) {
     tm->begin(0);
     hipLaunchKernelGGL(k_vmax, dim3((unsigned)p->n_time), dim3(256), 0, st, w.sv, w.counters + p->n_time,
                        p->n_bl, w.vmax);
@@ -648,7 +670,7 @@ static blink_status image_batch_impl(const blink_problem* p, const blink_inputs*
   if (p->n_bl == 0) a.vmax = nullptr;
   a.images = images;
   a.weight_sum = weight_sum;
-#define BLINK_IMAGE_CALL(n) image_n<n>(p, a, chunk, st, tm)
+#define BLINK_IMAGE_CALL(n) image_n<n>(p, a, chunk, st, tm, sorted)
   BLINK_DISPATCH_N(p->grid_n, BLINK_IMAGE_CALL)
 #undef BLINK_IMAGE_CALL
 }

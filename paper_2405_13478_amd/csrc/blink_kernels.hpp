@@ -67,6 +67,14 @@ struct SortArgs {
   const int* ant1;               // [B] (with cable lengths)
   const int* ant2;               // [B]
   int n_ant;                     // cable length entries; an antenna index outside [0, n_ant) adds 0
+  double* vmax;                  // [T] largest |v| of the usable baselines, or null
+  // single-image bounds (one channel per timestep): the cell bounds of image t
+  // are formed by the sort kernel itself (see k_sort_small)
+  int N, kw;                     // grid size, gridding kernel support (0: nearest cell)
+  double ndx;                    // fl(N * dx)
+  const double* freq;            // [1]
+  int* bnd;                      // [T][N + 2]
+  int* ncz;                      // [T]
 };
 
 // u l0 + v m0 + w (n0 - 1): the path difference (metres) between the new
@@ -149,14 +157,47 @@ __global__ void __launch_bounds__(1024) k_sort_run(SortArgs a) {
   if (threadIdx.x == 0 && s_unf) atomicAdd(&a.n_unflagged[t], s_unf);
 }
 
+// Cell bounds of one image from its sorted u (see k_bounds, which documents
+// them): ucol(j) is the clamped u cell of sorted position j. Run by one
+// workgroup; returns nothing, writes bnd[0 .. N + 1] and *ncz.
+template <class UCol>
+__device__ __forceinline__ void image_bounds(UCol&& ucol, int nv, int N, int kw, int* bnd, int* ncz) {
+  const int H = N / 2;
+  const int clast = nv == 0 ? -H - 1 : ucol(nv - 1);
+  if (nv > 16 * (N + 2)) {
+    for (int c = (int)threadIdx.x - H; c <= H + 1; c += blockDim.x) {
+      int lo = 0, hi = nv;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ucol(mid) >= c) hi = mid; else lo = mid + 1;
+      }
+      bnd[c + H] = lo;
+    }
+  } else {
+    for (int j = threadIdx.x; j < nv; j += blockDim.x) {
+      const int cj = ucol(j);
+      const int cp = j == 0 ? -H - 1 : ucol(j - 1);
+      for (int c = cp + 1; c <= cj; ++c) bnd[c + H] = j;
+    }
+    for (int c = clast + 1 + (int)threadIdx.x; c <= H + 1; c += blockDim.x) bnd[c + H] = nv;
+  }
+  // every entry lies in a column |c| <= max(|first|, |last|) of the sorted order;
+  // a gridding kernel reaches at most W/2 + 1 columns further
+  const int reach = kw > 0 ? kw / 2 + 1 : 0;
+  if (threadIdx.x == 0) *ncz = nv == 0 ? 0 : min(H, max(clast, -ucol(0)) + 1 + reach);
+}
+
 // Whole per-timestep order in one kernel when B <= RUN: load, bitonic sort in
-// LDS, then the sorted u, v, baseline index and the two counters of the
-// timestep (one workgroup per timestep, so no atomics and no initialisation).
-template <int RUN>
+// LDS, then the sorted u, v, baseline index, the two counters and the largest
+// |v| of the timestep (one workgroup per timestep, so no atomics and no
+// initialisation). BOUNDS (one channel per timestep): the same workgroup then
+// forms the cell bounds of its image, which saves the bounds launch.
+template <int RUN, bool BOUNDS = false>
 __global__ void __launch_bounds__(1024) k_sort_small(SortArgs a) {
   __shared__ unsigned long long sk[RUN];
   __shared__ int si[RUN];
   __shared__ int s_unf, s_val;
+  __shared__ double s_vm[1024 / WAVE];
   const int t = a.t0 + blockIdx.y;
   const size_t tb = (size_t)t * a.B;
   if (threadIdx.x == 0) { s_unf = 0; s_val = 0; }
@@ -196,16 +237,36 @@ __global__ void __launch_bounds__(1024) k_sort_small(SortArgs a) {
       __syncthreads();
     }
   }
+  double vm = 0.0;
   for (int j = threadIdx.x; j < a.B; j += blockDim.x) {
     const int b = si[j];
+    const double v = a.uvw[(tb + b) * 3 + 1];
     a.su[tb + j] = a.uvw[(tb + b) * 3 + 0];
-    a.sv[tb + j] = a.uvw[(tb + b) * 3 + 1];
+    a.sv[tb + j] = v;
     if (a.sd != nullptr) a.sd[tb + j] = baseline_delay(a, tb, b);
     a.perm[tb + j] = b;
+    if (j < s_val) vm = fmax(vm, fabs(v));        // usable entries sort first
   }
+  for (int o = WAVE / 2; o > 0; o >>= 1) vm = fmax(vm, __shfl_xor(vm, o));
+  if (threadIdx.x % WAVE == 0) s_vm[threadIdx.x / WAVE] = vm;
+  __syncthreads();
   if (threadIdx.x == 0) {
     a.n_unflagged[t] = s_unf;
     a.n_valid[t] = s_val;
+    if (a.vmax != nullptr) {
+      double m = 0.0;
+      for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) m = fmax(m, s_vm[w]);
+      a.vmax[t] = m;
+    }
+  }
+  if constexpr (BOUNDS) {
+    const double s = cells_per_metre(a.freq[0], a.ndx);
+    const int H = a.N / 2;
+    auto ucol = [&](int j) -> int {
+      const double x = rint(a.uvw[(tb + si[j]) * 3 + 0] * s);
+      return (int)fmin(fmax(x, (double)-H), (double)H);
+    };
+    image_bounds(ucol, s_val, a.N, a.kw, a.bnd + (size_t)t * (a.N + 2), a.ncz + t);
   }
 }
 
@@ -313,35 +374,12 @@ __global__ void __launch_bounds__(256) k_bounds(ImgArgs a) {
   const int t = img / a.C, ch = img - t * a.C;
   const double s = cells_per_metre(a.freq[ch], a.ndx);
   const int H = a.N / 2;
-  const int nv = a.n_valid[t];
   const double* su = a.su + (size_t)t * a.B;
-  int* bnd = a.bnd + (size_t)img * (a.N + 2);
-  auto col = [&](int j) -> int {
+  auto ucol = [&](int j) -> int {
     const double x = rint(su[j] * s);
     return (int)fmin(fmax(x, (double)-H), (double)H);
   };
-  const int clast = nv == 0 ? -H - 1 : col(nv - 1);
-  if (nv > 16 * (a.N + 2)) {
-    for (int c = (int)threadIdx.x - H; c <= H + 1; c += blockDim.x) {
-      int lo = 0, hi = nv;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (col(mid) >= c) hi = mid; else lo = mid + 1;
-      }
-      bnd[c + H] = lo;
-    }
-  } else {
-    for (int j = threadIdx.x; j < nv; j += blockDim.x) {
-      const int cj = col(j);
-      const int cp = j == 0 ? -H - 1 : col(j - 1);
-      for (int c = cp + 1; c <= cj; ++c) bnd[c + H] = j;
-    }
-    for (int c = clast + 1 + (int)threadIdx.x; c <= H + 1; c += blockDim.x) bnd[c + H] = nv;
-  }
-  // every entry lies in a column |c| <= max(|first|, |last|) of the sorted order;
-  // a gridding kernel reaches at most W/2 + 1 columns further
-  const int reach = a.kw > 0 ? a.kw / 2 + 1 : 0;
-  if (threadIdx.x == 0) a.ncz[img] = nv == 0 ? 0 : min(H, max(clast, -col(0)) + 1 + reach);
+  image_bounds(ucol, a.n_valid[t], a.N, a.kw, a.bnd + (size_t)img * (a.N + 2), a.ncz + img);
 }
 
 // Largest |v| in metres over the usable baselines of each timestep (one
