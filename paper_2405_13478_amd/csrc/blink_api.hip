@@ -345,7 +345,7 @@ void launch_cols_image(ImgArgs& a, int n, hipStream_t st) {
   using C_ = Cols<N, CPW>;
   a.wtiles = a.ntiles = (int)cdiv(N / 2, CPW);
   const dim3 g1((unsigned)(cdiv(n, 8) * 8LL * a.ntiles));
-  hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, UNI, CPW>), g1, dim3(C_::THREADS), C_::lds_bytes(UNI), st, a);
+  hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, UNI, CPW>), g1, dim3(C_::THREADS), C_::grid_lds_bytes(UNI), st, a);
 }
 
 template <int N, int CPW, bool UNI>
@@ -387,8 +387,8 @@ size_t cols_lds(int cpw, bool uni, bool kb) {
     return cpw == 2 ? ColsHalf<N, 2, false>::LDS : cpw == 4 ? ColsHalf<N, 4, false>::LDS
                                                             : ColsHalf<N, 8, false>::LDS;
   }
-  return cpw == 2 ? Cols<N, 2>::lds_bytes(uni) : cpw == 4 ? Cols<N, 4>::lds_bytes(uni)
-                                                          : Cols<N, 8>::lds_bytes(uni);
+  return cpw == 2 ? Cols<N, 2>::grid_lds_bytes(uni) : cpw == 4 ? Cols<N, 4>::grid_lds_bytes(uni)
+                                                          : Cols<N, 8>::grid_lds_bytes(uni);
 }
 constexpr size_t LDS_PER_CU = size_t(160) << 10;
 
@@ -452,7 +452,7 @@ blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t s
       a.ntiles = (int)cdiv(N / 2, CPW);
       const dim3 g1((unsigned)(cdiv(n, 8) * 8LL * a.ntiles));
       hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, false, CPW, true>), g1, dim3(C_::THREADS),
-                         C_::lds_bytes(false), st, a);
+                         C_::grid_lds_bytes(false), st, a);
     } else if (uni) {
       launch_cols_image<N, true>(a, n, cpw, st);
     } else {
@@ -474,7 +474,7 @@ template <int N>
 blink_status grid_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t st) {
   const long long n_img = (long long)p->n_time * p->n_chan;
   const bool uni = p->weighting == BLINK_UNIFORM;
-  const size_t lds1 = Cols<N>::lds_bytes(true);
+  const size_t lds1 = Cols<N>::grid_lds_bytes(true);
   a.wtiles = (int)cdiv(N, Cols<N>::CPW);
   hipLaunchKernelGGL(k_bounds, dim3((unsigned)n_img), dim3(256), 0, st, a);
   for (long long i0 = 0; i0 < n_img; i0 += chunk) {

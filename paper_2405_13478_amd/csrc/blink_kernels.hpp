@@ -497,7 +497,7 @@ __device__ __forceinline__ float2 rotate_phase(float2 v, double d, double f) {
 // flight. Only this wavefront touches the column, so the LDS adds happen in a
 // fixed order (steps in sequence; within a step, sub-steps in sequence and
 // lanes in LDS order).
-constexpr int GU = 4;
+constexpr int GU = 2;
 
 struct ColSpan {                 // the sorted entries of one u-cell column
   int dlo, dhi, clo, chi;        // direct range and mirror (conjugate) range
@@ -549,19 +549,64 @@ __device__ __forceinline__ void step_gather(const ImgArgs& a, int t, int ch, dou
   }
 }
 
+// ------------------------------------------------------ LDS accumulation
+// LDS floating-point atomic adds are slow on gfx950: measured at about 190
+// CU cycles per wave64 ds_add_f32, against about 5 for an integer atomic or a
+// plain read-modify-write. The column being gridded is LDS that only its own
+// wavefront writes, so the adds are done as plain read-modify-writes, and
+// lanes that would touch the same element take turns: each turn, every
+// pending lane posts a tag (turn * 64 + 64 - lane) to claim slot key mod 64
+// with an integer atomic max, and the lane whose tag survives adds its value
+// (and, with counts, 1 to its count). Lanes whose elements coincide share a
+// slot, so no two lanes of one turn touch one element; of the lanes sharing
+// a slot the lowest goes first, so each element receives its adds in lane
+// order, step after step: the order of the sorted list, whatever the
+// grouping into steps. Tags grow with the wavefront's turn counter, so the
+// claim slots never need clearing after their initial zeroing.
+constexpr int CLAIM_SLOTS = 64;
+
+struct Claim {
+  unsigned* slot;                // CLAIM_SLOTS words of this wavefront's LDS
+  unsigned turn;                 // wave-uniform
+};
+
+// Zeroes this wavefront's claim slots (the caller's next wave_sync publishes them).
+__device__ __forceinline__ Claim claim_init(unsigned* slots, int lane) {
+  if (lane < CLAIM_SLOTS) slots[lane] = 0u;
+  return Claim{slots, 0u};
+}
+
+// dst[idx] += v (and cnt[cidx] += 1 with COUNT) for every active lane; lanes
+// with equal idx must pass equal key.
+template <bool COUNT>
+__device__ __forceinline__ void wave_add(float2* dst, int idx, int* cnt, int cidx, int key, float2 v, bool active,
+                                         Claim& cl, int lane) {
+  bool pending = active;
+  while (__ballot(pending) != 0) {
+    const unsigned tag = cl.turn * CLAIM_SLOTS + (unsigned)(CLAIM_SLOTS - lane);
+    unsigned* slot = cl.slot + (key & (CLAIM_SLOTS - 1));
+    if (pending) __hip_atomic_fetch_max(slot, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    wave_sync();
+    if (pending && *slot == tag) {
+      const float2 d = dst[idx];
+      dst[idx] = make_float2(d.x + v.x, d.y + v.y);
+      if (COUNT) cnt[cidx] += 1;
+      pending = false;
+    }
+    wave_sync();
+    ++cl.turn;
+  }
+}
+
 // phase 3: the LDS adds; kd / kc count the kept direct / conjugate entries
 template <bool COUNT>
-__device__ __forceinline__ void step_add(const EntryStep& e, float2* buf, int* cnt, int& kd, int& kc) {
+__device__ __forceinline__ void step_add(const EntryStep& e, float2* buf, int* cnt, int& kd, int& kc, Claim& cl,
+                                         int lane) {
 #pragma unroll
   for (int u = 0; u < GU; ++u) {
-    if (e.ok[u]) {
-      float2 v = e.val[u];
-      if (e.cj[u]) v.y = -v.y;
-      float2* p = &buf[pad(e.row[u])];
-      atomicAdd(&p->x, v.x);
-      atomicAdd(&p->y, v.y);
-      if (COUNT) atomicAdd(&cnt[e.row[u]], 1);
-    }
+    float2 v = e.val[u];
+    if (e.cj[u]) v.y = -v.y;
+    wave_add<COUNT>(buf, pad(e.row[u]), cnt, e.row[u], e.row[u], v, e.ok[u], cl, lane);
     kd += __popcll(__ballot(e.ok[u] && !e.cj[u]));
     kc += __popcll(__ballot(e.ok[u] && e.cj[u]));
   }
@@ -572,20 +617,20 @@ __device__ __forceinline__ void step_add(const EntryStep& e, float2* buf, int* c
 // copy of the loop, so the plain one carries none of its work.
 template <int N, bool COUNT, bool ROT>
 __device__ __forceinline__ void grid_steps_t(const ImgArgs& a, const ColSpan& c, int i0, float2* buf, int* cnt,
-                                             int t, int ch, double s, int lane, int& kd, int& kc) {
+                                             int t, int ch, double s, int lane, int& kd, int& kc, Claim& cl) {
   const int total = c.total();
   for (; i0 < total; i0 += GU * WAVE) {
     EntryStep e;
     step_keys<ROT>(a, c, i0, t, lane, e);
     step_gather<N, ROT>(a, t, ch, s, e);
-    step_add<COUNT>(e, buf, cnt, kd, kc);
+    step_add<COUNT>(e, buf, cnt, kd, kc, cl, lane);
   }
 }
 template <int N, bool COUNT>
 __device__ __forceinline__ void grid_steps(const ImgArgs& a, const ColSpan& c, int i0, float2* buf, int* cnt,
-                                           int t, int ch, double s, int lane, int& kd, int& kc) {
-  if (a.sd != nullptr) grid_steps_t<N, COUNT, true>(a, c, i0, buf, cnt, t, ch, s, lane, kd, kc);
-  else grid_steps_t<N, COUNT, false>(a, c, i0, buf, cnt, t, ch, s, lane, kd, kc);
+                                           int t, int ch, double s, int lane, int& kd, int& kc, Claim& cl) {
+  if (a.sd != nullptr) grid_steps_t<N, COUNT, true>(a, c, i0, buf, cnt, t, ch, s, lane, kd, kc, cl);
+  else grid_steps_t<N, COUNT, false>(a, c, i0, buf, cnt, t, ch, s, lane, kd, kc, cl);
 }
 
 // ------------------------------------------------------------- kernel gridding
@@ -618,7 +663,7 @@ __device__ __forceinline__ float kb_taper(float xi, const ImgArgs& a) {
 template <int N, bool COUNT>
 __device__ __forceinline__ void grid_steps_kb(const ImgArgs& a, const ColSpan& sp, int c, float2* buf,
                                               int* cnt, int t, int ch, double s, int lane, int& kd,
-                                              int& kc, float& wsum) {
+                                              int& kc, float& wsum, Claim& cl) {
   constexpr int H = N / 2;
   const size_t tb = (size_t)t * a.B;
   const size_t vb = ((size_t)t * a.C + ch) * a.B;
@@ -644,21 +689,27 @@ __device__ __forceinline__ void grid_steps_kb(const ImgArgs& a, const ColSpan& s
     kd += __popcll(__ballot(home && !cj));
     kc += __popcll(__ballot(home && cj));
     const double du = (double)c - xu;
-    if (ok && fabs(du) <= hw) {
-      float2 v = load_vis(a, vb + b, b, ch);
+    const bool in = ok && fabs(du) <= hw;
+    float2 v = make_float2(0.f, 0.f);
+    float wu = 0.f;
+    int j0 = 0, j1 = -1;
+    if (in) {
+      v = load_vis(a, vb + b, b, ch);
       if (a.sd != nullptr) v = rotate_phase(v, a.sd[tb + j], a.freq[ch]);
       if (cj) v.y = -v.y;
-      const float wu = kb_weight((float)du, a);
-      const int j0 = (int)ceil(xv - hw), j1 = (int)floor(xv + hw);
-      for (int r = j0; r <= j1; ++r) {
-        const float w = wu * kb_weight((float)((double)r - xv), a);
-        const int row = r < 0 ? r + N : r;
-        float2* p = &buf[pad(row)];
-        atomicAdd(&p->x, w * v.x);
-        atomicAdd(&p->y, w * v.y);
-        if (COUNT) atomicAdd(&cnt[row], 1);
-        wsum += w;
-      }
+      wu = kb_weight((float)du, a);
+      j0 = (int)ceil(xv - hw);
+      j1 = (int)floor(xv + hw);
+    }
+    // footprint rows j0 + k, k = 0 .. W (a footprint spans W or W + 1 rows)
+    for (int k = 0; k <= a.kw; ++k) {
+      const int r = j0 + k;
+      const bool act = in && r <= j1;
+      float w = 0.f;
+      if (act) w = wu * kb_weight((float)((double)r - xv), a);
+      const int row = r < 0 ? r + N : r;
+      wave_add<COUNT>(buf, pad(row), cnt, row, row, make_float2(w * v.x, w * v.y), act, cl, lane);
+      if (act) wsum += w;
     }
   }
 }
@@ -692,6 +743,8 @@ struct Cols {
   static size_t lds_bytes(bool counts) {
     return (size_t)(CPW * STRIDE + TW) * sizeof(float2) + (counts ? (size_t)CPW * N * sizeof(int) : 0);
   }
+  // the gridding kernel adds every wavefront's claim slots after that
+  static size_t grid_lds_bytes(bool counts) { return lds_bytes(counts) + (size_t)CPW * CLAIM_SLOTS * sizeof(unsigned); }
 };
 
 // One workgroup = CPW consecutive u-cell columns of one image; one wavefront
@@ -741,6 +794,8 @@ __global__ void __launch_bounds__((Cols<N, CPW>::THREADS)) k_grid_cols(ImgArgs a
   for (int r = lane; r < C_::STRIDE; r += WAVE) buf[r] = make_float2(0.f, 0.f);
   if (CNT)
     for (int r = lane; r < N; r += WAVE) cnt[r] = 0;
+  unsigned* lclaim = reinterpret_cast<unsigned*>(lcnt + (CNT ? CPW * N : 0));
+  Claim cl = claim_init(lclaim + wave * CLAIM_SLOTS, lane);
   wave_sync();
 
   int kept_b = 0, wcontrib = 0;
@@ -751,7 +806,7 @@ __global__ void __launch_bounds__((Cols<N, CPW>::THREADS)) k_grid_cols(ImgArgs a
     const ColSpan span{at(cs - hk), at(cs + hk + 1), at(-cs - hk), at(-cs + hk + 1)};
     int kd = 0, kc = 0;
     float ws = 0.f;
-    grid_steps_kb<N, CNT>(a, span, cs, buf, cnt, t, ch, s, lane, kd, kc, ws);
+    grid_steps_kb<N, CNT>(a, span, cs, buf, cnt, t, ch, s, lane, kd, kc, ws, cl);
     wave_sync();
     kept_b = kd + ((MODE == MODE_IMAGE && cs > 0) ? kc : 0);
     for (int o = WAVE / 2; o > 0; o >>= 1) ws += __shfl_xor(ws, o);
@@ -760,7 +815,7 @@ __global__ void __launch_bounds__((Cols<N, CPW>::THREADS)) k_grid_cols(ImgArgs a
     const int* bnd = a.bnd + (size_t)img * (N + 2);
     const ColSpan span{bnd[cs + H], bnd[cs + 1 + H], bnd[-cs + H], bnd[-cs + 1 + H]};
     int kd = 0, kc = 0;
-    grid_steps<N, CNT>(a, span, 0, buf, cnt, t, ch, s, lane, kd, kc);
+    grid_steps<N, CNT>(a, span, 0, buf, cnt, t, ch, s, lane, kd, kc, cl);
     wave_sync();
     // baselines counted once: the direct entry of every cell column, plus the
     // conjugate entries of columns whose mirror the image path never visits
@@ -836,23 +891,20 @@ struct ColsHalf {
   static constexpr int THREADS = CPW * WAVE;
   static constexpr int TW = TwLds<N>::ON ? tw_entries(N) : 0;
   static constexpr size_t LDS = (size_t)(CPW * STRIDE + TW) * sizeof(float2) +
-                                (UNI ? (size_t)CPW * (N / 2) * sizeof(int) : 0);
+                                (UNI ? (size_t)CPW * (N / 2) * sizeof(int) : 0) +
+                                (size_t)CPW * CLAIM_SLOTS * sizeof(unsigned);
 };
 
 // LDS adds (and counts) of the kept entries of a step whose row lies in half HF
 template <int N, int HF, bool COUNT>
-__device__ __forceinline__ void step_add_half(const EntryStep& e, float2* hbuf, int* hcnt) {
+__device__ __forceinline__ void step_add_half(const EntryStep& e, float2* hbuf, int* hcnt, Claim& cl, int lane) {
 #pragma unroll
   for (int u = 0; u < GU; ++u) {
-    if (e.ok[u] && (e.row[u] >= N / 2) == (HF == 1)) {
-      float2 v = e.val[u];
-      if (e.cj[u]) v.y = -v.y;
-      const int r = e.row[u] - HF * (N / 2);
-      float2* p = &hbuf[pad(r)];
-      atomicAdd(&p->x, v.x);
-      atomicAdd(&p->y, v.y);
-      if (COUNT) atomicAdd(&hcnt[r], 1);
-    }
+    const bool act = e.ok[u] && (e.row[u] >= N / 2) == (HF == 1);
+    float2 v = e.val[u];
+    if (e.cj[u]) v.y = -v.y;
+    const int r = e.row[u] - HF * (N / 2);
+    wave_add<COUNT>(hbuf, pad(r), hcnt, r, r, v, act, cl, lane);
   }
 }
 
@@ -896,7 +948,7 @@ __device__ __forceinline__ int uniform_half(float2* hbuf, const int* hcnt, int l
 template <int N, bool ROT, bool UNI, int ZB>
 __device__ __forceinline__ void grid_col_half(const ImgArgs& a, const ColSpan& c, float2* hbuf, int* hcnt,
                                               HalfIn<N>& in, int t, int ch, double s, int lane, int& kd,
-                                              int& kc, int& occ) {
+                                              int& kc, int& occ, Claim& cl) {
   constexpr int R0 = HalfIn<N>::R;
   const int total = c.total();
   const bool one = total <= GU * WAVE;
@@ -907,7 +959,7 @@ __device__ __forceinline__ void grid_col_half(const ImgArgs& a, const ColSpan& c
     if (total > 0) {
       step_keys<ROT>(a, c, 0, t, lane, e);
       step_gather<N, ROT>(a, t, ch, s, e);
-      step_add_half<N, 0, UNI>(e, hbuf, hcnt);
+      step_add_half<N, 0, UNI>(e, hbuf, hcnt, cl, lane);
       step_count(e, kd, kc);
     }
   } else {
@@ -915,7 +967,7 @@ __device__ __forceinline__ void grid_col_half(const ImgArgs& a, const ColSpan& c
       EntryStep f;
       step_keys<ROT>(a, c, i0, t, lane, f);
       step_gather<N, ROT>(a, t, ch, s, f);
-      step_add_half<N, 0, UNI>(f, hbuf, hcnt);
+      step_add_half<N, 0, UNI>(f, hbuf, hcnt, cl, lane);
       step_count(f, kd, kc);
     }
   }
@@ -929,13 +981,13 @@ __device__ __forceinline__ void grid_col_half(const ImgArgs& a, const ColSpan& c
   zero_half<N, UNI>(hbuf, hcnt, lane);
   wave_sync();
   if (one) {
-    if (total > 0) step_add_half<N, 1, UNI>(e, hbuf, hcnt);
+    if (total > 0) step_add_half<N, 1, UNI>(e, hbuf, hcnt, cl, lane);
   } else {
     for (int i0 = 0; i0 < total; i0 += GU * WAVE) {
       EntryStep f;
       step_keys<ROT>(a, c, i0, t, lane, f);
       step_gather<N, ROT>(a, t, ch, s, f);
-      step_add_half<N, 1, UNI>(f, hbuf, hcnt);
+      step_add_half<N, 1, UNI>(f, hbuf, hcnt, cl, lane);
     }
   }
   wave_sync();
@@ -977,6 +1029,7 @@ __global__ void __launch_bounds__((ColsHalf<N, CPW, UNI>::THREADS)) k_grid_cols_
   const bool active = col < ncols;
   float2* hbuf = lds + wave * C_::STRIDE;
   int* hcnt = UNI ? lcnt + wave * H : nullptr;
+  unsigned* lclaim = reinterpret_cast<unsigned*>(lcnt + (UNI ? CPW * H : 0));
   const double s = cells_per_metre(a.freq[ch], a.ndx);
   const float2* tw = stage_twiddles<N>(ltw);
   // the only workgroup barrier: it publishes the LDS twiddles; after it every
@@ -994,8 +1047,9 @@ __global__ void __launch_bounds__((ColsHalf<N, CPW, UNI>::THREADS)) k_grid_cols_
     constexpr int ZB = decltype(zbc)::value;
     HalfIn<N> in;
     int kd = 0, kc = 0, occ = 0;
-    if (a.sd != nullptr) grid_col_half<N, true, UNI, ZB>(a, span, hbuf, hcnt, in, t, ch, s, lane, kd, kc, occ);
-    else grid_col_half<N, false, UNI, ZB>(a, span, hbuf, hcnt, in, t, ch, s, lane, kd, kc, occ);
+    Claim cl = claim_init(lclaim + wave * CLAIM_SLOTS, lane);
+    if (a.sd != nullptr) grid_col_half<N, true, UNI, ZB>(a, span, hbuf, hcnt, in, t, ch, s, lane, kd, kc, occ, cl);
+    else grid_col_half<N, false, UNI, ZB>(a, span, hbuf, hcnt, in, t, ch, s, lane, kd, kc, occ, cl);
     // baselines counted once: the direct entry of every cell column, plus the
     // conjugate entries of columns whose mirror the image path never visits
     const int kept_b = kd + (col > 0 ? kc : 0);
