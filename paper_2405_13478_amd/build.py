@@ -18,6 +18,24 @@ HIPCC_FLAGS = [
 ]
 
 
+PROBES = os.path.join(PKG, "probes")
+
+
+def build_probes(verbose: bool = False) -> None:
+    """The measurement probes under csrc/probes (stand-alone executables)."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(PROBES, exist_ok=True)
+    flags = [f for f in HIPCC_FLAGS if f not in ("-fPIC", "-shared")]
+    for src in sorted(os.listdir(os.path.join(CSRC, "probes"))):
+        if not src.endswith(".hip"):
+            continue
+        exe = os.path.join(PROBES, src[:-4])
+        cmd = [hipcc, *flags, "-I", CSRC, os.path.join(CSRC, "probes", src), "-o", exe]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+
+
 def build(verbose: bool = False) -> str:
     sys.path.insert(0, CSRC)
     try:
@@ -33,6 +51,7 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    build_probes(verbose)
     return LIB
 
 
