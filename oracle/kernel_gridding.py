@@ -23,8 +23,16 @@ names neither the kernel nor its correction; the readings used here are:
   (-j, -i) (its conjugate sits at -x).
 * A baseline is kept iff it is unflagged, finite and all its footprint cells
   satisfy |i| < N/2 and |j| < N/2 (so the grid stays exactly Hermitian).
-* Natural weighting only: G = S, W = the sum of every weight added (direct
-  and mirror). ``norm=1`` divides by W.
+* Natural weighting: G = S, W = the sum of every weight added (direct and
+  mirror). ``norm=1`` divides by W.
+* Uniform weighting (Sec. 4.4.2, every occupied uv cell counting equally),
+  read for a gridding kernel as a weight per visibility: baseline b gets
+  omega_b = 1 / n[k_b], n the number of kept entries (direct and mirror)
+  whose nearest cell is b's nearest cell k_b = (rint(x_v), rint(x_u)); it is
+  then gridded with the kernel as above with omega_b V' (and W sums
+  omega_b times every kernel weight added). With a box kernel of width 1 this
+  is exactly the nearest-cell uniform weighting (cell value = sum / count,
+  W = number of occupied cells).
 * Correction: the image pixel at offset (q_m, q_l) from the centre is divided
   by c(q_l / N) c(q_m / N), c the Fourier transform of the continuous kernel
   normalised to c(0) = 1. For the Kaiser-Bessel kernel it has the closed form
@@ -99,12 +107,29 @@ def conv_keep(xu, xv, support: int, grid_n: int, flagged=None):
     return keep
 
 
-def grid_conv(vis_prime, xu, xv, keep, grid_n: int, support: int, beta: float):
+def uniform_weights(xu, xv, keep, grid_n: int):
+    """omega_b = 1 / n[k_b] for kept b (0 otherwise): n counts the kept entries,
+    each baseline once at its nearest cell and once (its conjugate) at the
+    mirror cell."""
+    n_ = grid_n
+    k = np.flatnonzero(np.asarray(keep))
+    iu = np.rint(np.asarray(xu, dtype=np.float64)[k]).astype(np.int64)
+    iv = np.rint(np.asarray(xv, dtype=np.float64)[k]).astype(np.int64)
+    n = np.zeros((n_, n_), dtype=np.int64)
+    np.add.at(n, (np.mod(iv, n_), np.mod(iu, n_)), 1)
+    np.add.at(n, (np.mod(-iv, n_), np.mod(-iu, n_)), 1)
+    om = np.zeros(len(keep))
+    om[k] = 1.0 / n[np.mod(iv, n_), np.mod(iu, n_)]
+    return om
+
+
+def grid_conv(vis_prime, xu, xv, keep, grid_n: int, support: int, beta: float, omega=None):
     """Convolutional gridding: returns (S, counts, W).
 
     S[j mod N][i mod N] collects w V' over each kept baseline's footprint and
     w conj(V') at the mirror cells; counts holds the number of contributions
-    per cell and W the sum of all weights added.
+    per cell and W the sum of all weights added. ``omega`` (uniform
+    weighting) multiplies each baseline's weights.
     """
     n_ = grid_n
     S = np.zeros((n_, n_), dtype=np.complex128)
@@ -115,6 +140,8 @@ def grid_conv(vis_prime, xu, xv, keep, grid_n: int, support: int, beta: float):
         iu = footprint(xu[b], support)
         iv = footprint(xv[b], support)
         w = np.outer(kb(iv - xv[b], support, beta), kb(iu - xu[b], support, beta))   # [j][i]
+        if omega is not None:
+            w = w * omega[b]
         rows, cols = np.mod(iv, n_), np.mod(iu, n_)
         S[np.ix_(rows, cols)] += w * vp[b]
         cnt[np.ix_(rows, cols)] += 1
@@ -133,15 +160,17 @@ def correct_taper(img, grid_n: int, support: int, beta: float):
 
 
 def image_one_conv(vis, u_m, v_m, freq_hz, grid_n, pixscale, out_n, norm, support, beta=None,
-                   flagged=None, gains=None, ant1=None, ant2=None, correct=True):
-    """Dirty image of one (timestep, channel) with Kaiser-Bessel gridding."""
+                   flagged=None, gains=None, ant1=None, ant2=None, correct=True, weighting=0):
+    """Dirty image of one (timestep, channel) with Kaiser-Bessel gridding
+    (weighting 0 natural, 1 uniform)."""
     beta = kb_default_beta(support) if beta is None or beta < 0 else float(beta)
     s = uv_scale(freq_hz, grid_n, pixscale)
     xu = np.asarray(u_m, dtype=np.float64) * np.float64(s)
     xv = np.asarray(v_m, dtype=np.float64) * np.float64(s)
     keep = conv_keep(xu, xv, support, grid_n, flagged)
     vp = apply_gains(vis, gains, ant1, ant2)
-    S, cnt, W = grid_conv(vp, xu, xv, keep, grid_n, support, beta)
+    om = uniform_weights(xu, xv, keep, grid_n) if weighting == 1 else None
+    S, cnt, W = grid_conv(vp, xu, xv, keep, grid_n, support, beta, om)
     R = fft2(S, +1)
     n_ = grid_n
     img = np.real(np.roll(R, (n_ // 2, n_ // 2), axis=(-2, -1)))
@@ -155,7 +184,7 @@ def image_one_conv(vis, u_m, v_m, freq_hz, grid_n, pixscale, out_n, norm, suppor
 
 
 def image_batch_conv(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, norm, support, beta=None,
-                     flags=None, gains=None, ant1=None, ant2=None, images=None):
+                     flags=None, gains=None, ant1=None, ant2=None, images=None, weighting=0):
     """Images [len][M][M] and W [len] for flat indices t * C + c (default all)."""
     T, C, B = vis.shape
     idx = range(T * C) if images is None else list(images)
@@ -164,7 +193,7 @@ def image_batch_conv(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, norm, support
         t, c = divmod(int(i), C)
         r = image_one_conv(vis[t, c], uvw_m[t, :, 0], uvw_m[t, :, 1], freq_hz[c], grid_n, pixscale,
                            out_n, norm, support, beta, None if flags is None else flags[t],
-                           gains, ant1, ant2)
+                           gains, ant1, ant2, weighting=weighting)
         out.append(r["image"])
         ws.append(r["W"])
     return np.stack(out), np.asarray(ws)

@@ -126,3 +126,54 @@ def test_unit_source_at_phase_centre_has_peak_one():
     img = r["image"]
     assert np.unravel_index(np.argmax(img), img.shape) == (out_n // 2, out_n // 2)
     assert abs(img[out_n // 2, out_n // 2] - 1.0) <= 1e-12
+
+
+def test_uniform_box_kernel_of_width_one_is_nearest_cell_uniform():
+    """Uniform weighting with the one-cell box kernel: each cell holds the mean
+    of its visibilities and W is the number of occupied cells, exactly the
+    nearest-cell uniform weighting of the main oracle."""
+    rng = np.random.default_rng(17)
+    n, nb = 32, 400
+    xu = rng.uniform(-10, 10, nb)                 # dense enough to put several entries in a cell
+    xv = rng.uniform(-10, 10, nb)
+    xu[:30] = np.round(xu[:30])                   # and some baselines on the same cell centres
+    xv[:30] = np.round(xv[:30])
+    vp = rng.normal(size=nb) + 1j * rng.normal(size=nb)
+    keep = kg.conv_keep(xu, xv, 1, n)
+    om = kg.uniform_weights(xu, xv, keep, n)
+    S, cnt, W = kg.grid_conv(vp, xu, xv, keep, n, 1, 0.0, om)
+    iu, iv, keep0 = oracle.cell_index(xu, xv, 1.0, n)
+    S0, cnt0 = oracle.grid(vp, iu, iv, keep0, n)
+    G0, W0 = oracle.weight(S0, cnt0, 1)
+    assert cnt0.max() >= 3
+    assert np.allclose(S, G0, rtol=0, atol=1e-12)
+    assert abs(W - W0) <= 1e-9 and W0 == np.count_nonzero(cnt0)
+
+
+def test_uniform_weights_sum_to_one_per_occupied_cell():
+    # sum over the entries (direct and mirror) at a cell of omega = 1 for every occupied cell
+    rng = np.random.default_rng(19)
+    n, nb = 64, 500
+    xu = rng.uniform(-20, 20, nb)
+    xv = rng.uniform(-20, 20, nb)
+    keep = kg.conv_keep(xu, xv, 6, n)
+    om = kg.uniform_weights(xu, xv, keep, n)
+    tot = np.zeros((n, n))
+    k = np.flatnonzero(keep)
+    iu, iv = np.rint(xu[k]).astype(int), np.rint(xv[k]).astype(int)
+    np.add.at(tot, (np.mod(iv, n), np.mod(iu, n)), om[k])
+    np.add.at(tot, (np.mod(-iv, n), np.mod(-iu, n)), om[k])
+    occ = tot > 0
+    assert np.allclose(tot[occ], 1.0, rtol=0, atol=1e-12)
+
+
+def test_uniform_kernel_unit_source_at_centre_peaks_at_one():
+    rng = np.random.default_rng(23)
+    n, nb, f = 64, 200, oracle.C_LIGHT
+    u = rng.uniform(-25, 25, nb)
+    v = rng.uniform(-25, 25, nb)
+    vis = np.ones(nb, complex)
+    r = kg.image_one_conv(vis, u, v, f, n, 1.0 / n, n, 1, 6, weighting=1)
+    img = r["image"]
+    assert abs(img[n // 2, n // 2] - 1.0) <= 1e-12
+    assert np.unravel_index(np.argmax(img), img.shape) == (n // 2, n // 2)
