@@ -59,15 +59,18 @@
  *   C(i - x_u) C(j - x_v) V' to every cell with |i - x_u| <= W/2 and
  *   |j - x_v| <= W/2 (and the same weight times conj(V') at the mirror
  *   cells), C(d) = I0(beta sqrt(1 - (2d/W)^2)) / I0(beta). It is kept iff
- *   that whole footprint satisfies |i| < N/2, |j| < N/2. Natural weighting
- *   only: W = the sum of all weights added. Each image pixel at offset
+ *   that whole footprint satisfies |i| < N/2, |j| < N/2. W = the sum of all
+ *   weights added. UNIFORM (Sec. 4.4.2 read together with 4.4.1) multiplies
+ *   every weight of baseline b by 1 / n_b, n_b the number of kept entries,
+ *   direct and mirrored, whose nearest cell (rint(x_u), rint(x_v)) is b's
+ *   own (so the one-cell box kernel, W = 1 with beta = 0, gives the
+ *   nearest-cell uniform image). Each image pixel at offset
  *   (q_m, q_l) from the centre is divided by c(q_l/N) c(q_m/N), c the
  *   kernel's continuous Fourier transform normalised to c(0) = 1:
  *   c(xi) = [sinh(z)/z] / [sinh(beta)/beta], z = sqrt(beta^2 - (pi W xi)^2)
  *   (sin(|z|)/|z| where pi W |xi| > beta). Weights are evaluated in FP32 from
  *   the FP64 distances; blink_grid returns counts of contributions per cell.
- *   Uniform weighting and blink_degrid_adjoint with a kernel return
- *   BLINK_E_UNSUPPORTED.
+ *   blink_degrid_adjoint with a kernel returns BLINK_E_UNSUPPORTED.
  * - Phase rotation (phase_l, phase_m != 0; Sec. 4.2 (iii)): correlation
  *   phases the visibilities to zenith; each V' is multiplied by
  *   exp(+2 pi i (u l0 + v m0 + w (n0 - 1)) nu_c / c0), n0 = sqrt(1 - l0^2 -

@@ -85,6 +85,7 @@ struct Work {
   float2* half;
   float2* gamma;
   float2* pacc;
+  int* kdens;         // kernel gridding with uniform weighting: [chunk][B]
 };
 
 int default_chunk(const blink_problem* p, int call, long long n_img) {
@@ -131,6 +132,8 @@ size_t carve(const blink_problem* p, int call, int chunk, char* base, Work* w) {
     x.gamma = (float2*)take((size_t)chunk * B * 8);
     x.pacc = (float2*)take(B * 8);
   }
+  if (call != BLINK_CALL_ADJOINT && p->kernel_support > 0 && p->weighting == BLINK_UNIFORM)
+    x.kdens = (int*)take((size_t)chunk * B * 4);
   if (w) *w = x;
   return o;
 }
@@ -163,8 +166,7 @@ blink_status validate_problem(const blink_problem* p, int call) {
   if (T * C > INT32_MAX || T * B > INT32_MAX) return BLINK_E_SIZE;
   if ((double)T * C * B > 9.0e18 || (double)T * C * N * N > 9.0e18) return BLINK_E_SIZE;
   if (!n_supported(p->grid_n)) return BLINK_E_UNSUPPORTED;
-  if (p->kernel_support > 0 && (p->weighting != BLINK_NATURAL || call == BLINK_CALL_ADJOINT))
-    return BLINK_E_UNSUPPORTED;
+  if (p->kernel_support > 0 && call == BLINK_CALL_ADJOINT) return BLINK_E_UNSUPPORTED;
   return BLINK_OK;
 }
 
@@ -330,6 +332,7 @@ ImgArgs make_args(const blink_problem* p, const blink_inputs* in, const Work& w)
   a.vmax = w.vmax;
   a.bnd = w.bnd; a.ncz = w.ncz; a.wpart = w.wpart; a.kpart = w.kpart; a.wstride = w.wstride;
   a.half = w.half; a.gamma = w.gamma; a.pacc = w.pacc;
+  a.kdens = w.kdens;
   a.kw = p->kernel_support;
   if (a.kw > 0) {
     const double beta = p->kernel_beta < 0 ? kb_default_beta(a.kw) : p->kernel_beta;
@@ -338,6 +341,13 @@ ImgArgs make_args(const blink_problem* p, const blink_inputs* in, const Work& w)
     a.ktaper0 = (float)(beta > 0 ? sinh(beta) / beta : 1.0);
   }
   return a;
+}
+
+// per-entry cell occupancy for kernel gridding with uniform weighting
+template <int N>
+void launch_kb_density(const ImgArgs& a, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_kb_density<N>, dim3((unsigned)n), dim3(DENS_WAVES * WAVE),
+                     (size_t)DENS_WAVES * N * sizeof(int), st, a);
 }
 
 template <int N, bool UNI, int CPW>
@@ -445,6 +455,11 @@ blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t s
   for (long long i0 = 0; i0 < n_img; i0 += chunk) {
     const int n = (int)std::min<long long>(chunk, n_img - i0);
     a.img0 = (int)i0; a.nimg = n;
+    if (a.kdens != nullptr) {
+      T_.begin(2);
+      launch_kb_density<N>(a, n, st);
+      T_.end();
+    }
     T_.begin(2);
     if (kb) {
       constexpr int CPW = cols_per_wg(N);
@@ -482,6 +497,7 @@ blink_status grid_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t st
     a.img0 = (int)i0; a.nimg = n;
     a.ntiles = (int)cdiv(N, Cols<N>::CPW);
     const dim3 g1((unsigned)(cdiv(n, 8) * 8LL * a.ntiles));
+    if (a.kdens != nullptr) launch_kb_density<N>(a, n, st);
     if (p->kernel_support > 0)
       hipLaunchKernelGGL((k_grid_cols<N, MODE_GRID, false, Cols<N>::CPW, true>), g1, dim3(Cols<N>::THREADS),
                          lds1, st, a);

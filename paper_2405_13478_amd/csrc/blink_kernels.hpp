@@ -360,6 +360,9 @@ struct ImgArgs {
   float kbeta;                  // shape
   float kinv;                   // 1 / I0(kbeta)
   float ktaper0;                // sinh(kbeta) / kbeta: the correction's value at 0 before normalising
+  // kernel gridding with uniform weighting: [chunk][B] per sorted entry, the
+  // kept entries (direct and mirrored) at its nearest cell; null otherwise
+  int* kdens;
 };
 
 // bnd[c + N/2] = first sorted position j with clamp(rint(u_j s)) >= c for
@@ -663,7 +666,7 @@ __device__ __forceinline__ float kb_taper(float xi, const ImgArgs& a) {
 template <int N, bool COUNT>
 __device__ __forceinline__ void grid_steps_kb(const ImgArgs& a, const ColSpan& sp, int c, float2* buf,
                                               int* cnt, int t, int ch, double s, int lane, int& kd,
-                                              int& kc, float& wsum, Claim& cl) {
+                                              int& kc, float& wsum, Claim& cl, const int* dens) {
   constexpr int H = N / 2;
   const size_t tb = (size_t)t * a.B;
   const size_t vb = ((size_t)t * a.C + ch) * a.B;
@@ -698,6 +701,8 @@ __device__ __forceinline__ void grid_steps_kb(const ImgArgs& a, const ColSpan& s
       if (a.sd != nullptr) v = rotate_phase(v, a.sd[tb + j], a.freq[ch]);
       if (cj) v.y = -v.y;
       wu = kb_weight((float)du, a);
+      // uniform weighting: the baseline's share of its nearest cell
+      if (dens != nullptr) wu = wu / (float)dens[j];
       j0 = (int)ceil(xv - hw);
       j1 = (int)floor(xv + hw);
     }
@@ -719,6 +724,80 @@ __host__ __device__ constexpr int cols_per_wg(int n) { return n <= 1024 ? 8 : (n
 
 // Twiddle table staged in LDS (one copy per workgroup) where it fits beside
 // the transform buffers without lowering occupancy.
+// Uniform weighting with kernel gridding: the weight of a kept baseline is
+// 1 / n, n the number of kept entries - direct and mirrored - whose nearest
+// cell is the baseline's own. This pass writes n for every kept entry of each
+// image of the chunk into a.kdens[li][j] (j its sorted position). One
+// workgroup per image, DENS_WAVES wavefronts; a wavefront takes signed
+// u-cell columns c in turn, counts the kept direct entries of column c and
+// the mirrored entries of column -c per row in an LDS row array with integer
+// atomics, reads the counts back for the direct entries, and clears only the
+// rows it touched. Kept entries have |nearest cell| <= N/2 - 1 on both axes,
+// so the columns -N/2+1 .. N/2-1 hold all of them.
+constexpr int DENS_WAVES = 4;
+
+template <int N>
+__global__ void __launch_bounds__(DENS_WAVES * WAVE) k_kb_density(ImgArgs a) {
+  extern __shared__ int dens_lds[];
+  constexpr int H = N / 2;
+  const int li = blockIdx.x;
+  if (li >= a.nimg) return;
+  const int img = a.img0 + li;
+  const int t = img / a.C, ch = img - t * a.C;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), lane = threadIdx.x % WAVE;
+  int* rc = dens_lds + wave * N;                     // rc[iv + H]: entries in row iv of the column
+  for (int r = lane; r < N; r += WAVE) rc[r] = 0;
+  wave_sync();
+  const int* bnd = a.bnd + (size_t)img * (N + 2);
+  const double s = cells_per_metre(a.freq[ch], a.ndx);
+  const double hw = 0.5 * a.kw;
+  const double* su = a.su + (size_t)t * a.B;
+  const double* sv = a.sv + (size_t)t * a.B;
+  int* out = a.kdens + (size_t)li * a.B;
+  // nearest row of entry j (mirrored with mj), or N when it is not kept
+  auto row_of = [&](int j, bool mj) -> int {
+    const double xu = su[j] * s, xv = sv[j] * s;
+    const bool kept = ceil(xu - hw) > (double)-H && floor(xu + hw) < (double)H &&
+                      ceil(xv - hw) > (double)-H && floor(xv + hw) < (double)H;
+    if (!kept) return N;
+    const int r = (int)rint(xv);
+    return mj ? -r : r;
+  };
+  // 64 columns per round: lane l fetches the ranges of column c0 + l
+  for (int c0 = -H + 1 + wave * WAVE; c0 < H; c0 += DENS_WAVES * WAVE) {
+    const int cl_ = c0 + lane;
+    int d0 = 0, d1 = 0, m0 = 0, m1 = 0;
+    if (cl_ < H) {
+      d0 = bnd[cl_ + H]; d1 = bnd[cl_ + 1 + H];
+      m0 = bnd[-cl_ + H]; m1 = bnd[-cl_ + 1 + H];
+    }
+    unsigned long long busy = __ballot(d1 > d0);     // columns with direct entries
+    while (busy != 0ull) {
+      const int k = __builtin_ctzll(busy);
+      busy &= busy - 1ull;
+      const int dlo = __shfl(d0, k), dhi = __shfl(d1, k), mlo = __shfl(m0, k), mhi = __shfl(m1, k);
+      const int nd = dhi - dlo, total = nd + (mhi - mlo);
+      for (int i = lane; i < total; i += WAVE) {
+        const bool mj = i >= nd;
+        const int r = row_of(mj ? mlo + (i - nd) : dlo + i, mj);
+        if (r != N) atomicAdd(&rc[r + H], 1);
+      }
+      wave_sync();
+      for (int i = lane; i < nd; i += WAVE) {
+        const int r = row_of(dlo + i, false);
+        if (r != N) out[dlo + i] = rc[r + H];
+      }
+      wave_sync();
+      for (int i = lane; i < total; i += WAVE) {
+        const bool mj = i >= nd;
+        const int r = row_of(mj ? mlo + (i - nd) : dlo + i, mj);
+        if (r != N) rc[r + H] = 0;
+      }
+      wave_sync();
+    }
+  }
+}
+
 template <int N>
 struct TwLds { static constexpr bool ON = N <= 1024; };
 
@@ -754,10 +833,12 @@ struct Cols {
 // The 1D grid is laid out so that all column tiles of an image share one XCD
 // (workgroup L runs on XCD L mod 8): the image's visibility row and the
 // timestep's sorted lists are then fetched into a single L2.
-// KB: Kaiser-Bessel kernel gridding (natural weighting) instead of nearest cell.
+// KB: Kaiser-Bessel kernel gridding instead of nearest cell; uniform weighting
+// then comes from the per-entry cell occupancy of k_kb_density (a.kdens), so
+// UNI (the nearest-cell division by counts) stays off.
 template <int N, int MODE, bool UNI, int CPW = cols_per_wg(N), bool KB = false>
 __global__ void __launch_bounds__((Cols<N, CPW>::THREADS)) k_grid_cols(ImgArgs a) {
-  static_assert(!(KB && UNI), "kernel gridding is natural-weighting only");
+  static_assert(!(KB && UNI), "kernel gridding weights uniformly through a.kdens");
   extern __shared__ float4 lds_raw[];
   __shared__ int red[2 * CPW];
   using C_ = Cols<N, CPW>;
@@ -806,7 +887,8 @@ __global__ void __launch_bounds__((Cols<N, CPW>::THREADS)) k_grid_cols(ImgArgs a
     const ColSpan span{at(cs - hk), at(cs + hk + 1), at(-cs - hk), at(-cs + hk + 1)};
     int kd = 0, kc = 0;
     float ws = 0.f;
-    grid_steps_kb<N, CNT>(a, span, cs, buf, cnt, t, ch, s, lane, kd, kc, ws, cl);
+    const int* dens = a.kdens != nullptr ? a.kdens + (size_t)li * a.B : nullptr;
+    grid_steps_kb<N, CNT>(a, span, cs, buf, cnt, t, ch, s, lane, kd, kc, ws, cl, dens);
     wave_sync();
     kept_b = kd + ((MODE == MODE_IMAGE && cs > 0) ? kc : 0);
     for (int o = WAVE / 2; o > 0; o >>= 1) ws += __shfl_xor(ws, o);

@@ -82,7 +82,6 @@ def _image(lib, p, inp, images=FAKE, ws=None, nbytes=0):
     (dict(kernel_support=1, kernel_beta=-1.0), E_ARG),        # default shape needs W >= 2
     (dict(kernel_support=4, kernel_beta=float("nan")), E_ARG),
     (dict(kernel_support=4, kernel_beta=float("inf")), E_ARG),
-    (dict(kernel_support=4, kernel_beta=-1.0, weighting=1), E_UNSUP),   # natural weighting only
     (dict(phase_l=float("nan")), E_ARG), (dict(phase_l=0.8, phase_m=0.6), E_ARG),   # needs l^2 + m^2 < 1
     (dict(phase_m=float("inf")), E_ARG),
 ])
@@ -166,6 +165,21 @@ def test_workspace_sizes_scale(lib):
     c3.chunk_images = 8
     s8 = lib.blink_workspace_size(ctypes.byref(c3), 1)
     assert s8 - s4 >= 4 * 512 * 512 * 8
+
+
+def test_uniform_kernel_gridding_sizes_its_density_table(lib):
+    # uniform weighting with a gridding kernel passes validation and takes
+    # one int per (image of a chunk, baseline) for the cell occupancy
+    for call in (0, 1):
+        nat = _prob(kernel_support=4, kernel_beta=-1.0, chunk_images=3)
+        uni = _prob(kernel_support=4, kernel_beta=-1.0, chunk_images=3, weighting=1)
+        s_nat = lib.blink_workspace_size(ctypes.byref(nat), call)
+        s_uni = lib.blink_workspace_size(ctypes.byref(uni), call)
+        assert s_uni - s_nat == -(-3 * 10 * 4 // 256) * 256
+        assert _image(lib, uni, _inputs(), ws=None, nbytes=0) == E_WS
+    # nearest-cell uniform weighting needs no such table
+    assert lib.blink_workspace_size(ctypes.byref(_prob(weighting=1)), 1) == \
+        lib.blink_workspace_size(ctypes.byref(_prob()), 1)
 
 
 def test_kernel_gridding_has_no_adjoint(lib):
