@@ -38,11 +38,55 @@ def test_taper_beta_zero_is_sinc():
         assert abs(kg.kb_taper(xi, 3, 0.0) - ref) <= 1e-14
 
 
-def test_default_beta_values():
-    # pi sqrt(0.5625 W^2 - 0.8) for alpha = 2
-    assert abs(kg.kb_default_beta(6) - math.pi * math.sqrt(0.5625 * 36 - 0.8)) <= 1e-12
+@pytest.mark.parametrize("support", [2, 4, 6, 8])
+def test_default_beta_puts_first_transform_zero_at_alias_edge(support):
+    # Beatty et al. (2005) choose beta for a grid alpha = 2 times the kept
+    # image so that the kernel transform's first zero sits at the edge of the
+    # alias band, 1 - 1/(2 alpha) = 0.75 cycles per cell, nudged just outside
+    # it by their empirical -0.8. Located here by quadrature of the kernel
+    # itself and root finding, independent of the closed-form taper.
+    from scipy import integrate, optimize
+
+    beta = kg.kb_default_beta(support)
+    h = support / 2.0
+
+    def c(xi):
+        return integrate.quad(lambda d: float(kg.kb(d, support, beta)) * math.cos(2 * math.pi * xi * d),
+                              -h, h, limit=200, epsabs=1e-13)[0]
+
+    grid = np.arange(0.0, 1.0, 0.025)
+    vals = [c(x) for x in grid]
+    k = next(i for i in range(len(vals) - 1) if vals[i] > 0 >= vals[i + 1])
+    xi0 = optimize.brentq(c, grid[k], grid[k + 1], xtol=1e-12)
+    assert 0.75 < xi0 < 0.75 + 0.2 / support ** 2, xi0
+
+
+def test_default_beta_needs_support_two():
     with pytest.raises(ValueError):
         kg.kb_default_beta(1)
+
+
+@pytest.mark.parametrize("support", [1, 2, 3, 4, 5, 6])
+def test_footprint_and_keep_rule_by_enumeration(support):
+    # footprint = every integer cell within W/2 of x (inclusive); kept iff all
+    # of them on both axes lie in |i| < N/2. Checked by enumerating cells at
+    # positions on a 1/8-cell lattice that includes exact integers and
+    # half-integers near both edges.
+    n = 16
+    h = support / 2.0
+    xs = np.arange(-n / 2 - 2, n / 2 + 2 + 1e-9, 0.125)
+    cells = np.arange(-2 * n, 2 * n + 1)
+    def brute(x):
+        return cells[np.abs(cells - x) <= h]
+    for x in xs:
+        assert np.array_equal(kg.footprint(float(x), support), brute(x))
+    xu, xv = np.meshgrid(xs, xs[::3])
+    xu, xv = xu.ravel(), xv.ravel()
+    got = kg.conv_keep(xu, xv, support, n)
+    inside = lambda x: bool(np.all(np.abs(brute(x)) < n / 2))
+    want = np.array([inside(a) and inside(b) for a, b in zip(xu, xv)])
+    assert np.array_equal(got, want)
+    assert 0 < want.sum() < len(want)
 
 
 def test_box_kernel_of_width_one_is_nearest_cell_gridding():
