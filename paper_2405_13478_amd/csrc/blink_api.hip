@@ -43,6 +43,8 @@ bool n_supported(int n) {
 inline size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int KB_MAX_SUPPORT = 16;
+// supports up to this take the kernel-gridding form with fewer row-weight registers
+constexpr int KB_SMALL_SUPPORT = 8;
 
 // A phase centre other than zenith asks for the geometric rotation.
 inline bool rotates(const blink_problem* p) { return p->phase_l != 0.0 || p->phase_m != 0.0; }
@@ -66,6 +68,23 @@ double bessel_i0(double x) {
     sum += term;
   }
   return sum;
+}
+
+// Coefficients c_k = (beta^2 / 4)^k / ((k!)^2 I0(beta)) of the Kaiser-Bessel
+// weight as a power series in w = 1 - (2d/W)^2; the series form is switched on
+// when the terms beyond the kept ones add less than 1e-8 at w = 1 (all terms
+// are positive and, past k = beta / 2, shrink by the ratio q below).
+void kb_series(double beta, ImgArgs* a) {
+  const double q4 = 0.25 * beta * beta;
+  const double i0 = bessel_i0(beta);
+  double c = 1.0 / i0;
+  for (int k = 0; k < KB_POLY_TERMS; ++k) {
+    if (k > 0) c *= q4 / ((double)k * k);
+    a->kpoly[k] = (float)c;
+  }
+  const double next = c * q4 / ((double)KB_POLY_TERMS * KB_POLY_TERMS);
+  const double q = q4 / ((double)(KB_POLY_TERMS + 1) * (KB_POLY_TERMS + 1));
+  a->kpoly_on = q < 0.5 && next / (1.0 - q) < 1e-8 ? 1 : 0;
 }
 
 struct Work {
@@ -339,6 +358,8 @@ ImgArgs make_args(const blink_problem* p, const blink_inputs* in, const Work& w)
     a.kbeta = (float)beta;
     a.kinv = (float)(1.0 / bessel_i0(beta));
     a.ktaper0 = (float)(beta > 0 ? sinh(beta) / beta : 1.0);
+    a.k2w = (float)(2.0 / a.kw);
+    kb_series(beta, &a);
   }
   return a;
 }
@@ -466,8 +487,12 @@ blink_status image_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t s
       using C_ = Cols<N, CPW>;
       a.ntiles = (int)cdiv(N / 2, CPW);
       const dim3 g1((unsigned)(cdiv(n, 8) * 8LL * a.ntiles));
-      hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, false, CPW, true>), g1, dim3(C_::THREADS),
-                         C_::grid_lds_bytes(false), st, a);
+      if (p->kernel_support <= KB_SMALL_SUPPORT)
+        hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, false, CPW, true, KB_SMALL_SUPPORT>), g1, dim3(C_::THREADS),
+                           C_::grid_lds_bytes(false), st, a);
+      else
+        hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, false, CPW, true, KB_MAX_SUPPORT>), g1, dim3(C_::THREADS),
+                           C_::grid_lds_bytes(false), st, a);
     } else if (uni) {
       launch_cols_image<N, true>(a, n, cpw, st);
     } else {
@@ -498,9 +523,12 @@ blink_status grid_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t st
     a.ntiles = (int)cdiv(N, Cols<N>::CPW);
     const dim3 g1((unsigned)(cdiv(n, 8) * 8LL * a.ntiles));
     if (a.kdens != nullptr) launch_kb_density<N>(a, n, st);
-    if (p->kernel_support > 0)
-      hipLaunchKernelGGL((k_grid_cols<N, MODE_GRID, false, Cols<N>::CPW, true>), g1, dim3(Cols<N>::THREADS),
-                         lds1, st, a);
+    if (p->kernel_support > KB_SMALL_SUPPORT)
+      hipLaunchKernelGGL((k_grid_cols<N, MODE_GRID, false, Cols<N>::CPW, true, KB_MAX_SUPPORT>), g1,
+                         dim3(Cols<N>::THREADS), lds1, st, a);
+    else if (p->kernel_support > 0)
+      hipLaunchKernelGGL((k_grid_cols<N, MODE_GRID, false, Cols<N>::CPW, true, KB_SMALL_SUPPORT>), g1,
+                         dim3(Cols<N>::THREADS), lds1, st, a);
     else if (uni)
       hipLaunchKernelGGL((k_grid_cols<N, MODE_GRID, true>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
     else

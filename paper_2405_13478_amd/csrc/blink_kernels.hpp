@@ -317,6 +317,9 @@ __global__ void __launch_bounds__(256) k_sort_finish(SortArgs a, int src) {
 }
 
 // ============================================================== cell bounds
+// terms of the power series of the Kaiser-Bessel weight (see kb_weight)
+constexpr int KB_POLY_TERMS = 25;
+
 struct ImgArgs {
   int T, C, B, N, M, weighting, norm, vis_type;
   double ndx;                   // fl(N * dx)
@@ -360,6 +363,9 @@ struct ImgArgs {
   float kbeta;                  // shape
   float kinv;                   // 1 / I0(kbeta)
   float ktaper0;                // sinh(kbeta) / kbeta: the correction's value at 0 before normalising
+  float k2w;                    // 2 / W
+  int kpoly_on;                 // 1: weights from kpoly, 0: from cyl_bessel_i0f
+  float kpoly[KB_POLY_TERMS];   // C as a power series in 1 - (2d/W)^2 (see kb_weight)
   // kernel gridding with uniform weighting: [chunk][B] per sorted entry, the
   // kept entries (direct and mirrored) at its nearest cell; null otherwise
   int* kdens;
@@ -638,9 +644,22 @@ __device__ __forceinline__ void grid_steps(const ImgArgs& a, const ColSpan& c, i
 
 // ------------------------------------------------------------- kernel gridding
 // Kaiser-Bessel weight C(d) = I0(beta sqrt(1 - (2d/W)^2)) / I0(beta), |d| <= W/2.
+// I0(beta sqrt(w)) = sum_k (beta^2 w / 4)^k / (k!)^2 is a power series in
+// w = 1 - (2d/W)^2 in [0, 1] with positive coefficients, so Horner's rule in
+// FP32 evaluates it without cancellation; the host supplies the first
+// KB_POLY_TERMS coefficients divided by I0(beta) when the remaining tail is
+// below 1e-8 (beta up to about 20, which covers the default shape up to
+// W = 8), and the weights otherwise come from cyl_bessel_i0f.
 __device__ __forceinline__ float kb_weight(float d, const ImgArgs& a) {
-  const float t = 2.0f * d / (float)a.kw;
-  return cyl_bessel_i0f(a.kbeta * sqrtf(fmaxf(0.0f, 1.0f - t * t))) * a.kinv;
+  const float t = d * a.k2w;
+  const float w = fmaxf(0.0f, fmaf(-t, t, 1.0f));
+  if (a.kpoly_on) {
+    float p = a.kpoly[KB_POLY_TERMS - 1];
+#pragma unroll
+    for (int k = KB_POLY_TERMS - 2; k >= 0; --k) p = fmaf(p, w, a.kpoly[k]);
+    return p;
+  }
+  return cyl_bessel_i0f(a.kbeta * sqrtf(w)) * a.kinv;
 }
 
 // Normalised transform of the continuous kernel at xi cycles per cell:
@@ -655,15 +674,47 @@ __device__ __forceinline__ float kb_taper(float xi, const ImgArgs& a) {
   return f / a.ktaper0;
 }
 
+// Adds w[k] v to rows j0 + k, k < nrow, of this column for every active
+// lane, with one claim per entry instead of one per row: lanes with the same
+// first row j0 take turns, lowest lane first (the claim protocol of
+// wave_add, keyed on j0), and lanes with different j0 never reach the same
+// row at the same k, so a turn adds all of its lanes' rows in sequence over
+// k. Each element receives its adds in a fixed order: step, turn, k.
+template <int N, bool COUNT, int KMAX>
+__device__ __forceinline__ void kb_add_rows(float2* buf, int* cnt, int j0, int nrow, const float (&w)[KMAX + 1],
+                                            float2 v, bool active, int kw, Claim& cl, int lane) {
+  bool pending = active;
+  while (__ballot(pending) != 0) {
+    const unsigned tag = cl.turn * CLAIM_SLOTS + (unsigned)(CLAIM_SLOTS - lane);
+    unsigned* slot = cl.slot + (j0 & (CLAIM_SLOTS - 1));
+    if (pending) __hip_atomic_fetch_max(slot, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    wave_sync();
+    const bool go = pending && *slot == tag;
+#pragma unroll
+    for (int k = 0; k <= KMAX; ++k) {
+      if (k > kw) break;
+      if (go && k < nrow) {
+        const int r = j0 + k < 0 ? j0 + k + N : j0 + k;
+        const float2 d = buf[pad(r)];
+        buf[pad(r)] = make_float2(d.x + w[k] * v.x, d.y + w[k] * v.y);
+        if (COUNT) cnt[r] += 1;
+      }
+      wave_sync();
+    }
+    pending = pending && !go;
+    ++cl.turn;
+  }
+}
+
 // Kernel gridding of u-cell column c: the span holds the sorted entries whose
 // nearest column lies within W/2 + 1 of c (direct) and of -c (mirror). Each
 // direct entry at exact position x adds C(c - x_u) C(j - x_v) V' to the rows j
 // of its footprint, each mirror entry (its conjugate, at -x) adds
-// C(c + x_u) C(j + x_v) conj(V'). One entry per lane per step; within a step
-// the footprint rows are added in sequence, lanes in LDS order, so the order
-// of the adds is fixed. kd / kc count kept entries whose nearest column is c
-// (each baseline once); wsum collects this lane's weights.
-template <int N, bool COUNT>
+// C(c + x_u) C(j + x_v) conj(V'). One entry per lane per step; its W + 1
+// row weights are formed first (KMAX >= W bounds them at compile time), then
+// kb_add_rows adds them. kd / kc count kept entries whose nearest column is
+// c (each baseline once); wsum collects this lane's weights.
+template <int N, bool COUNT, int KMAX>
 __device__ __forceinline__ void grid_steps_kb(const ImgArgs& a, const ColSpan& sp, int c, float2* buf,
                                               int* cnt, int t, int ch, double s, int lane, int& kd,
                                               int& kc, float& wsum, Claim& cl, const int* dens) {
@@ -671,6 +722,7 @@ __device__ __forceinline__ void grid_steps_kb(const ImgArgs& a, const ColSpan& s
   const size_t tb = (size_t)t * a.B;
   const size_t vb = ((size_t)t * a.C + ch) * a.B;
   const double hw = 0.5 * a.kw;
+  const int kw = a.kw;
   const int nd = sp.nd(), total = sp.total();
   for (int i0 = 0; i0 < total; i0 += WAVE) {
     const int i = i0 + lane;
@@ -695,7 +747,7 @@ __device__ __forceinline__ void grid_steps_kb(const ImgArgs& a, const ColSpan& s
     const bool in = ok && fabs(du) <= hw;
     float2 v = make_float2(0.f, 0.f);
     float wu = 0.f;
-    int j0 = 0, j1 = -1;
+    int j0 = 0, nrow = 0;
     if (in) {
       v = load_vis(a, vb + b, b, ch);
       if (a.sd != nullptr) v = rotate_phase(v, a.sd[tb + j], a.freq[ch]);
@@ -704,26 +756,25 @@ __device__ __forceinline__ void grid_steps_kb(const ImgArgs& a, const ColSpan& s
       // uniform weighting: the baseline's share of its nearest cell
       if (dens != nullptr) wu = wu / (float)dens[j];
       j0 = (int)ceil(xv - hw);
-      j1 = (int)floor(xv + hw);
+      nrow = (int)floor(xv + hw) - j0 + 1;       // W or W + 1 rows
     }
-    // footprint rows j0 + k, k = 0 .. W (a footprint spans W or W + 1 rows)
-    for (int k = 0; k <= a.kw; ++k) {
-      const int r = j0 + k;
-      const bool act = in && r <= j1;
-      float w = 0.f;
-      if (act) w = wu * kb_weight((float)((double)r - xv), a);
-      const int row = r < 0 ? r + N : r;
-      wave_add<COUNT>(buf, pad(row), cnt, row, row, make_float2(w * v.x, w * v.y), act, cl, lane);
-      if (act) wsum += w;
+    float w[KMAX + 1];
+#pragma unroll
+    for (int k = 0; k <= KMAX; ++k) {
+      w[k] = 0.f;
+      if (k > kw) break;
+      if (k < nrow) {
+        w[k] = wu * kb_weight((float)((double)(j0 + k) - xv), a);
+        wsum += w[k];
+      }
     }
+    kb_add_rows<N, COUNT, KMAX>(buf, cnt, j0, nrow, w, v, in, kw, cl, lane);
   }
 }
 
 // u-cell columns (one wavefront each) per workgroup of the column kernels
 __host__ __device__ constexpr int cols_per_wg(int n) { return n <= 1024 ? 8 : (n <= 2048 ? 4 : 2); }
 
-// Twiddle table staged in LDS (one copy per workgroup) where it fits beside
-// the transform buffers without lowering occupancy.
 // Uniform weighting with kernel gridding: the weight of a kept baseline is
 // 1 / n, n the number of kept entries - direct and mirrored - whose nearest
 // cell is the baseline's own. This pass writes n for every kept entry of each
@@ -798,6 +849,8 @@ __global__ void __launch_bounds__(DENS_WAVES * WAVE) k_kb_density(ImgArgs a) {
   }
 }
 
+// Twiddle table staged in LDS (one copy per workgroup) where it fits beside
+// the transform buffers without lowering occupancy.
 template <int N>
 struct TwLds { static constexpr bool ON = N <= 1024; };
 
@@ -836,7 +889,8 @@ struct Cols {
 // KB: Kaiser-Bessel kernel gridding instead of nearest cell; uniform weighting
 // then comes from the per-entry cell occupancy of k_kb_density (a.kdens), so
 // UNI (the nearest-cell division by counts) stays off.
-template <int N, int MODE, bool UNI, int CPW = cols_per_wg(N), bool KB = false>
+// KMAX: largest support W the kernel gridding form handles (rows k = 0 .. W).
+template <int N, int MODE, bool UNI, int CPW = cols_per_wg(N), bool KB = false, int KMAX = 16>
 __global__ void __launch_bounds__((Cols<N, CPW>::THREADS)) k_grid_cols(ImgArgs a) {
   static_assert(!(KB && UNI), "kernel gridding weights uniformly through a.kdens");
   extern __shared__ float4 lds_raw[];
@@ -888,7 +942,7 @@ __global__ void __launch_bounds__((Cols<N, CPW>::THREADS)) k_grid_cols(ImgArgs a
     int kd = 0, kc = 0;
     float ws = 0.f;
     const int* dens = a.kdens != nullptr ? a.kdens + (size_t)li * a.B : nullptr;
-    grid_steps_kb<N, CNT>(a, span, cs, buf, cnt, t, ch, s, lane, kd, kc, ws, cl, dens);
+    grid_steps_kb<N, CNT, KMAX>(a, span, cs, buf, cnt, t, ch, s, lane, kd, kc, ws, cl, dens);
     wave_sync();
     kept_b = kd + ((MODE == MODE_IMAGE && cs > 0) ? kc : 0);
     for (int o = WAVE / 2; o > 0; o >>= 1) ws += __shfl_xor(ws, o);

@@ -46,8 +46,10 @@ def _run(w, d, support, beta=-1.0, weighting=0, **kw):
     return img, ws
 
 
-@pytest.mark.parametrize("name,support", [("plain128", 4), ("plain128", 6), ("allsky180", 4),
-                                          ("wide512", 6), ("wide512", 8)])
+# W <= 8 takes the weight's power series and the short footprint form; W = 12
+# the Bessel routine and the long form
+@pytest.mark.parametrize("name,support", [("plain128", 4), ("plain128", 6), ("plain128", 12),
+                                          ("allsky180", 4), ("wide512", 6), ("wide512", 8)])
 def test_kernel_image_parity(name, support):
     print(f"\n[gpu] kernel gridding {name} W={support}", flush=True)
     w = _case(name)
