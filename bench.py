@@ -129,6 +129,14 @@ EXTRA_STATS = {
     "xengine": ("stats_xengine", "--workload xengine --steps 5 --warmup 1 --no-cpu-baseline",
                 "k_xengine_256ant_4096samp_kernel_stats.md",
                 "X-engine, 256 antennas, 32 channels x 64 integrations of 4096 int8 samples"),
+    "diff": ("stats_diff", "--workload diff --steps 5 --warmup 2 --no-cpu-baseline",
+             "k_rows_adj_k_cols_adj_diff_widefield1024_320img_kernel_stats.md",
+             "forward + hand-written adjoint (autograd step) of 320 widefield images, 1024^2 -> 512^2, "
+             "with antenna gains"),
+    "allsky": ("stats_allsky", "--workload allsky --steps 3 --warmup 1 --no-cpu-baseline",
+               "k_grid_cols_k_rows_allsky180_uniform_kernel_stats.md",
+               "station all-sky, 32640 baselines, 32,000 images of 180^2 per step, uniform weighting, "
+               "2-10% flagged"),
 }
 
 
