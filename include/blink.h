@@ -321,7 +321,8 @@ typedef enum { BLINK_REF_NONE = 0, BLINK_REF_MEAN = 1, BLINK_REF_MODEL = 2 } bli
  * converted to float (exact below 2^24 in magnitude). The plain sum, not
  * the average, is returned.
  * Errors: BLINK_E_SIZE for negative sizes, n_ant < 2 with T*C > 0, n_samp not
- * a multiple of 16 or above 65536, or counts beyond 2^62; BLINK_E_ARG for null
+ * a multiple of 16 or above 65520 (the int32 sums of 2 n_samp products of
+ * magnitude up to 128^2 stay below 2^31), or counts beyond 2^62; BLINK_E_ARG for null
  * or misaligned required pointers. No workspace; enqueued on `stream`.
  */
 blink_status blink_correlate(const int8_t* volt, int32_t n_time, int32_t n_chan, int32_t n_ant,

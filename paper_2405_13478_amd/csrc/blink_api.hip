@@ -898,7 +898,7 @@ blink_status blink_correlate(const int8_t* volt, int32_t n_time, int32_t n_chan,
   if (n_time < 0 || n_chan < 0 || n_ant < 0 || n_samp < 0) return BLINK_E_SIZE;
   const long long nimg = (long long)n_time * n_chan;
   if (nimg == 0) return BLINK_OK;
-  if (n_ant < 2 || n_samp % 16 != 0 || n_samp > 65536) return BLINK_E_SIZE;
+  if (n_ant < 2 || n_samp % 16 != 0 || n_samp > XE_MAX_SAMPLES) return BLINK_E_SIZE;
   if ((double)nimg * n_ant * n_samp * 2 > 4.0e18) return BLINK_E_SIZE;
   if (!vis || (n_samp > 0 && !volt)) return BLINK_E_ARG;
   if ((uintptr_t)volt % 16 != 0) return BLINK_E_ARG;

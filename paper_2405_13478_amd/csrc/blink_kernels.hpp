@@ -1641,20 +1641,28 @@ __global__ void __launch_bounds__(DS_THREADS) k_dynspec(const float* __restrict_
 //   Re V_ij = sum r_i r_j + q_i q_j,   Im V_ij = sum q_i r_j - r_i q_j,
 // i.e. integer matrix products of the antenna-by-sample matrices R and Q.
 // One wavefront computes a 64 x 64 tile of antenna pairs (tile row I <= tile
-// column J) as 2 x 2 blocks of 32 x 32 with v_mfma_i32_32x32x32_i8, 32
-// samples per step: each lane loads 16 complex samples (32 bytes) of each of
-// its two row antennas and two column antennas, splits real and imaginary
-// bytes with byte permutes, and issues 16 products into twelve int32
-// accumulator sets (RR + QQ, QR, RQ per block); every loaded operand feeds
-// two blocks. Loads run two steps ahead of the products. Sums are exact in
-// int32 for up to 65536 samples. The workgroups of one (t, c) run on one XCD,
-// so its voltages are read from HBM once and served to every tile from L2.
+// column J) as 4 x 4 blocks of 16 x 16 with v_mfma_i32_16x16x64_i8, 64
+// samples per step: lane (g, q) holds antenna q of a block and the 16
+// samples 16 g .. 16 g + 15 of the step, so one 16-byte load instruction
+// reads 16 antenna rows, 64 contiguous bytes of each (a 32 x 32 block with
+// one antenna per lane would touch 64 rows per instruction, and the vector
+// memory path, which handles each touched line in turn, then sets the pace).
+// Each lane loads 32 bytes of each of its four row and four column antennas,
+// splits real and imaginary bytes with byte permutes, and issues 64 products
+// into 48 int32 accumulator sets (RR + QQ, QR, RQ per block); every operand
+// feeds four blocks. The next step's loads are in flight during the
+// products. A and B see the same sample order in every lane, so the dot
+// products do not depend on how the matrix cores order k within a lane.
+// Sums are exact in int32 for up to 65520 samples. The workgroups of one
+// (t, c) run on one XCD, so its voltages are read from HBM once and served to
+// every tile from L2.
 typedef int xe_v4i __attribute__((ext_vector_type(4)));
-typedef int xe_v16i __attribute__((ext_vector_type(16)));
-
-constexpr int XE_BLK = 32;      // antennas per MFMA block
-constexpr int XE_TILE = 64;     // antennas per wavefront tile edge (2 blocks)
-constexpr int XE_STEP = 32;     // samples per MFMA step (16 per half-wavefront)
+constexpr int XE_BLK = 16;      // antennas per MFMA block
+constexpr int XE_NB = 4;        // blocks per tile edge
+constexpr int XE_TILE = XE_BLK * XE_NB;   // antennas per wavefront tile edge
+constexpr int XE_STEP = 64;     // samples per MFMA step (16 per quarter-wavefront)
+// RR + QQ of S samples reaches 2 S 128^2 in magnitude: below 2^31 up to this S
+constexpr int XE_MAX_SAMPLES = 65520;
 
 struct XeArgs {
   const int8_t* volt;           // [T][C][A][S][2]
@@ -1680,6 +1688,7 @@ __device__ __forceinline__ void xe_split(const uint4 lo, const uint4 hi, xe_v4i&
 }
 
 __global__ void __launch_bounds__(WAVE) k_xengine(XeArgs a) {
+  constexpr int NOP = 2 * XE_NB;                              // operand antennas per lane
   const long long L = blockIdx.x;
   const long long r8 = L >> 3;
   const long long img = (r8 / a.npairs) * 8 + (L & 7);
@@ -1689,77 +1698,89 @@ __global__ void __launch_bounds__(WAVE) k_xengine(XeArgs a) {
   while (pr >= a.nt - ti) { pr -= a.nt - ti; ++ti; }
   const int tj = ti + pr;
   const int lane = threadIdx.x;
-  const int h = lane >> 5, q = lane & 31;
+  const int g = lane >> 4, q = lane & 15;
   const size_t rowb = (size_t)a.S * 2;                        // bytes per antenna row
   const int8_t* base = a.volt + (size_t)img * a.A * rowb;
-  // operand antennas of this lane: rows ti*64 + {0, 32} + q, columns tj*64 + {0, 32} + q
-  const uint4* pa[4];
-  bool ok[4];
+  // operand antennas of this lane: rows ti*64 + 16k + q, columns tj*64 + 16k + q
+  const uint4* pa[NOP];
+  bool ok[NOP];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int ant = (k < 2 ? ti : tj) * XE_TILE + (k & 1) * XE_BLK + q;
+  for (int k = 0; k < NOP; ++k) {
+    const int ant = (k < XE_NB ? ti : tj) * XE_TILE + (k % XE_NB) * XE_BLK + q;
     ok[k] = ant < a.A;
     pa[k] = reinterpret_cast<const uint4*>(base + (size_t)(ok[k] ? ant : 0) * rowb);
   }
-  xe_v16i acc[2][2][3];
+  xe_v4i acc[XE_NB][XE_NB][3];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < XE_NB; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < XE_NB; ++y)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) acc[x][y][k] = xe_v16i{0};
+      for (int k = 0; k < 3; ++k) acc[x][y][k] = xe_v4i{0, 0, 0, 0};
   const uint4 z = make_uint4(0u, 0u, 0u, 0u);
   // operand bytes of step s0 (zeros beyond S or beyond A). Unconditional
   // 16-byte loads from a clamped, valid address (antenna 0, first chunk),
   // zeroed afterwards, so no branches sit in the load path.
-  auto fetch = [&](int s0, uint4 (&f)[8]) {
-    const int s = s0 + 16 * h;                                // this half-wavefront's 16 samples
+  uint4 f[2 * NOP];
+  auto fetch = [&](int s0) {
+    const int s = s0 + 16 * g;                                // this quarter-wavefront's 16 samples
     const bool in = s < a.S;                                  // S is a multiple of 16
     const int u = in ? s >> 3 : 0;                            // uint4 index: 8 samples per 16 bytes
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < NOP; ++k) {
       f[2 * k] = pa[k][u];
       f[2 * k + 1] = pa[k][u + 1];
       if (!(ok[k] && in)) { f[2 * k] = z; f[2 * k + 1] = z; }
     }
   };
-  uint4 f0[8], f1[8];
-  if (a.S > 0) fetch(0, f0);                                  // (no samples: nothing to read)
+  xe_v4i r[NOP], qv[NOP];
+  auto split = [&]() {
+#pragma unroll
+    for (int k = 0; k < NOP; ++k) xe_split(f[2 * k], f[2 * k + 1], r[k], qv[k]);
+  };
+  if (a.S > 0) {                                              // (no samples: nothing to read)
+    fetch(0);
+    split();
+  }
   for (int s0 = 0; s0 < a.S; s0 += XE_STEP) {
-    fetch(s0 + XE_STEP, f1);
-    xe_v4i r[4], qv[4];
+    fetch(s0 + XE_STEP);
+    // the two products into one accumulator set are 32 issues apart
 #pragma unroll
-    for (int k = 0; k < 4; ++k) xe_split(f0[2 * k], f0[2 * k + 1], r[k], qv[k]);
+    for (int x = 0; x < XE_NB; ++x)
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+      for (int y = 0; y < XE_NB; ++y)
+        acc[x][y][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(r[x], r[XE_NB + y], acc[x][y][0], 0, 0, 0);
 #pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        xe_v16i* c = acc[x][y];
-        c[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(r[x], r[2 + y], c[0], 0, 0, 0);
-        c[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(qv[x], r[2 + y], c[1], 0, 0, 0);
-        c[2] = __builtin_amdgcn_mfma_i32_32x32x32_i8(r[x], qv[2 + y], c[2], 0, 0, 0);
-        c[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(qv[x], qv[2 + y], c[0], 0, 0, 0);
+    for (int x = 0; x < XE_NB; ++x)
+#pragma unroll
+      for (int y = 0; y < XE_NB; ++y) {
+        acc[x][y][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(qv[x], r[XE_NB + y], acc[x][y][1], 0, 0, 0);
+        acc[x][y][2] = __builtin_amdgcn_mfma_i32_16x16x64_i8(r[x], qv[XE_NB + y], acc[x][y][2], 0, 0, 0);
       }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) f0[k] = f1[k];
+    for (int x = 0; x < XE_NB; ++x)
+#pragma unroll
+      for (int y = 0; y < XE_NB; ++y)
+        acc[x][y][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(qv[x], qv[XE_NB + y], acc[x][y][0], 0, 0, 0);
+    split();
   }
-  // accumulator r of lane (h, q) in block (x, y) holds row
-  // i = ti*64 + 32x + (r % 4) + 8 (r / 4) + 4 h and column j = tj*64 + 32y + q
+  // accumulator element e of lane (g, q) in block (x, y) holds row
+  // i = ti*64 + 16x + 4g + e and column j = tj*64 + 16y + q
   const size_t nbl = (size_t)a.A * (a.A - 1) / 2;
   float2* v = a.vis + (size_t)img * nbl;
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < XE_NB; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
+    for (int y = 0; y < XE_NB; ++y) {
       const int j = tj * XE_TILE + y * XE_BLK + q;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = ti * XE_TILE + x * XE_BLK + (r & 3) + 8 * (r >> 2) + 4 * h;
+      for (int e = 0; e < 4; ++e) {
+        const int i = ti * XE_TILE + x * XE_BLK + 4 * g + e;
         if (j < a.A && i < j) {
           const size_t b = (size_t)i * a.A - (size_t)i * (i + 1) / 2 + (j - i - 1);
-          v[b] = make_float2((float)acc[x][y][0][r], (float)(acc[x][y][1][r] - acc[x][y][2][r]));
+          v[b] = make_float2((float)acc[x][y][0][e], (float)(acc[x][y][1][e] - acc[x][y][2][e]));
         } else if (a.autos != nullptr && i == j && j < a.A) {
-          a.autos[(size_t)img * a.A + i] = (float)acc[x][y][0][r];
+          a.autos[(size_t)img * a.A + i] = (float)acc[x][y][0][e];
         }
       }
     }

@@ -209,7 +209,7 @@ def test_correlate_validation(lib):
     assert c(FAKE, -1, 2, 8, 32, FAKE, None, None) == E_SIZE
     assert c(FAKE, 1, 1, 1, 32, FAKE, None, None) == E_SIZE            # one antenna: no pairs
     assert c(FAKE, 1, 1, 8, 24, FAKE, None, None) == E_SIZE            # samples not a multiple of 16
-    assert c(FAKE, 1, 1, 8, 65552, FAKE, None, None) == E_SIZE         # int32 sums could overflow
+    assert c(FAKE, 1, 1, 8, 65536, FAKE, None, None) == E_SIZE         # int32 sums could overflow
     assert c(None, 1, 1, 8, 32, FAKE, None, None) == E_ARG
     assert c(FAKE, 1, 1, 8, 32, None, None, None) == E_ARG
     assert c(ctypes.c_void_p(0x100008), 1, 1, 8, 32, FAKE, None, None) == E_ARG   # misaligned

@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("T,C,A,S", [(2, 3, 37, 48), (1, 1, 2, 16), (2, 2, 64, 1024), (1, 1, 256, 256),
-                                     (1, 2, 33, 32), (3, 1, 100, 0)])
+                                     (1, 2, 33, 32), (3, 1, 100, 0), (1, 1, 130, 208), (2, 1, 17, 80)])
 def test_correlate_matches_oracle(T, C, A, S):
     print(f"\n[gpu] correlate T={T} C={C} A={A} S={S}", flush=True)
     rng = np.random.default_rng(A * 1000 + S + T)
@@ -41,6 +41,22 @@ def test_correlate_extremes_beyond_float_precision():
     vis, autos = blink.correlate(torch.from_numpy(volt).to(device()), autos=True)
     torch.cuda.synchronize()
     rv, ra = xc.correlate(volt)
+    got = vis.cpu().numpy()
+    assert np.array_equal(got.real, rv.real.astype(np.float32))
+    assert np.array_equal(got.imag, rv.imag.astype(np.float32))
+    assert np.array_equal(autos.cpu().numpy(), ra.astype(np.float32))
+
+
+def test_correlate_largest_sample_count_stays_exact():
+    # -128 everywhere at the largest accepted count: RR + QQ = 2 * 16384 * 65520,
+    # just below 2^31, so the int32 sums must not wrap
+    S = 65520
+    volt = np.full((1, 1, 20, S, 2), -128, dtype=np.int8)
+    volt[0, 0, 3, ::7, 0] = 127
+    vis, autos = blink.correlate(torch.from_numpy(volt).to(device()), autos=True)
+    torch.cuda.synchronize()
+    rv, ra = xc.correlate(volt)
+    assert ra.max() == 2 * 16384 * S
     got = vis.cpu().numpy()
     assert np.array_equal(got.real, rv.real.astype(np.float32))
     assert np.array_equal(got.imag, rv.imag.astype(np.float32))
