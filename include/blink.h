@@ -75,8 +75,15 @@
  *   phases the visibilities to zenith; each V' is multiplied by
  *   exp(+2 pi i (u l0 + v m0 + w (n0 - 1)) nu_c / c0), n0 = sqrt(1 - l0^2 -
  *   m0^2), so that a source at (l0, m0) becomes a constant and images at the
- *   centre. (u, v, w) are not re-projected: the image stays on the zenith
- *   tangent plane, shifted by (l0, m0). The delay is formed in double at the
+ *   centre. With reproject = 0, (u, v, w) are not re-projected: the image
+ *   stays on the zenith tangent plane, shifted by (l0, m0). With reproject =
+ *   1 the image lies on the tangent plane at s0 = (l0, m0, n0): each baseline
+ *   is gridded at u' = b.e_u', v' = b.e_v' (metres, in double), the axes
+ *   e_u' = (n0 + m0^2 k, -l0 m0 k, -l0), e_v' = (-l0 m0 k, n0 + l0^2 k, -m0),
+ *   k = 1 / (1 + n0): the zenith frame's east and north axes carried by the
+ *   smallest rotation that takes zenith to s0; a source at direction
+ *   cosines (l', m') of that frame images at (l', m'). reproject is ignored
+ *   at (0, 0) and must be 0 or 1. The delay is formed in double at the
  *   sort, the phase in cycles in double, its sine and cosine in float.
  *   blink_degrid_adjoint applies the conjugate factor to the gradients.
  * - Cable correction (blink_inputs.cable_m != NULL; Sec. 4.2 (i)): antenna
@@ -146,6 +153,8 @@ typedef struct {
   double  phase_l;       /* phase centre (direction cosines relative to zenith) for    */
   double  phase_m;       /* the geometric rotation at load; (0, 0) = zenith, none;     */
                          /* l^2 + m^2 < 1                                               */
+  int32_t reproject;     /* 1: image on the tangent plane at (phase_l, phase_m)        */
+                         /* (baselines re-projected, see below); 0: zenith plane       */
 } blink_problem;
 
 typedef struct {          /* device pointers; the optional ones may be NULL            */

@@ -49,7 +49,8 @@ class Problem(ctypes.Structure):
                 ("norm", ctypes.c_int32), ("vis_type", ctypes.c_int32),
                 ("chunk_images", ctypes.c_int32), ("cols_per_wg", ctypes.c_int32),
                 ("rows_wg", ctypes.c_int32), ("kernel_support", ctypes.c_int32),
-                ("kernel_beta", ctypes.c_double), ("phase_l", ctypes.c_double), ("phase_m", ctypes.c_double)]
+                ("kernel_beta", ctypes.c_double), ("phase_l", ctypes.c_double), ("phase_m", ctypes.c_double),
+                ("reproject", ctypes.c_int32)]
 
 
 class Inputs(ctypes.Structure):
@@ -145,7 +146,8 @@ def _check(code, what):
 
 def make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n=None, weighting=NATURAL,
                  norm=NORM_WEIGHTS, gains=None, chunk_images=0, cols_per_wg=0, rows_wg=0,
-                 kernel_support=0, kernel_beta=-1.0, phase_lm=(0.0, 0.0), cable_m=None) -> Problem:
+                 kernel_support=0, kernel_beta=-1.0, phase_lm=(0.0, 0.0), cable_m=None,
+                 reproject=False) -> Problem:
     if vis.dtype == torch.complex64:
         T, C, B = vis.shape
         vt = VIS_C64
@@ -162,7 +164,8 @@ def make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n=None, weighting=NA
                    pixscale=float(pixscale), weighting=int(weighting), norm=int(norm),
                    vis_type=vt, chunk_images=int(chunk_images), cols_per_wg=int(cols_per_wg),
                    rows_wg=int(rows_wg), kernel_support=int(kernel_support),
-                   kernel_beta=float(kernel_beta), phase_l=float(phase_lm[0]), phase_m=float(phase_lm[1]))
+                   kernel_beta=float(kernel_beta), phase_l=float(phase_lm[0]), phase_m=float(phase_lm[1]),
+                   reproject=int(bool(reproject)))
 
 
 def make_inputs(p: Problem, vis, uvw_m, freq_hz, flags=None, vis_scale=None, ant1=None,
@@ -212,13 +215,14 @@ def image_batch(vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None, weighting=
                 norm=NORM_WEIGHTS, flags=None, vis_scale=None, ant1=None, ant2=None, gains=None,
                 chunk_images=None, cols_per_wg=None, rows_wg=None, images=None, weight_sum=None,
                 ws=None, stream=None, times=None, kernel_support=0, kernel_beta=-1.0, phase_lm=(0.0, 0.0),
-                cable_m=None):
+                cable_m=None, reproject=False):
     """Dirty images [T*C][M][M] float32 of the cube (blink_image_batch).
 
     Tunables left as None come from the autotuner's cache for this shape.
     ``kernel_support`` W >= 1 grids with a Kaiser-Bessel kernel of W cells
     (shape ``kernel_beta``, < 0 for the default) and corrects the image for it.
-    ``phase_lm`` = (l0, m0) rotates the phase centre from zenith to that direction.
+    ``phase_lm`` = (l0, m0) rotates the phase centre from zenith to that direction;
+    with ``reproject`` the image lies on the tangent plane at (l0, m0).
     ``cable_m`` [A] float64 electrical cable lengths (with ``ant1``/``ant2``)
     applies the cable correction exp(+2 pi i nu (l_ant1 - l_ant2) / c).
     With ``times`` (a KernelTimes) the instrumented twin blink_image_batch_timed
@@ -229,7 +233,7 @@ def image_batch(vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None, weighting=
     tun = tuning_for(grid_n, M, vis.shape[2], weighting, _vis_type(vis), chunk_images, cols_per_wg, rows_wg)
     p = make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, weighting, norm, gains, **tun,
                      kernel_support=kernel_support, kernel_beta=kernel_beta, phase_lm=phase_lm,
-                     cable_m=cable_m)
+                     cable_m=cable_m, reproject=reproject)
     inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains, cable_m)
     n_img, M = p.n_time * p.n_chan, p.out_n
     if images is None:
@@ -269,12 +273,12 @@ def image_batch_noalloc(images, vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=
 
 def grid(vis, uvw_m, freq_hz, *, grid_n, pixscale, weighting=NATURAL, flags=None, vis_scale=None,
          ant1=None, ant2=None, gains=None, counts=True, chunk_images=0, stream=None,
-         kernel_support=0, kernel_beta=-1.0, phase_lm=(0.0, 0.0), cable_m=None):
+         kernel_support=0, kernel_beta=-1.0, phase_lm=(0.0, 0.0), cable_m=None, reproject=False):
     """(weighted grid [T*C][N][N] c64, counts int32 or None, W float32, n_dropped int32)."""
     lib = load_library()
     p = make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, grid_n, weighting, NORM_NONE, gains,
                      chunk_images, kernel_support=kernel_support, kernel_beta=kernel_beta, phase_lm=phase_lm,
-                     cable_m=cable_m)
+                     cable_m=cable_m, reproject=reproject)
     inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains, cable_m)
     n_img, N, dev = p.n_time * p.n_chan, grid_n, vis.device
     g = torch.empty((n_img, N, N), dtype=torch.complex64, device=dev)
@@ -306,17 +310,17 @@ def fft2d(x, sign=+1, out=None, stream=None):
 def degrid_adjoint(image_grad, vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None,
                    weighting=NATURAL, norm=NORM_WEIGHTS, flags=None, ant1=None, ant2=None,
                    gains=None, want_gain_grad=True, chunk_images=0, stream=None, weight_sum=None,
-                   vis_scale=None, phase_lm=(0.0, 0.0), cable_m=None):
+                   vis_scale=None, phase_lm=(0.0, 0.0), cable_m=None, reproject=False):
     """(vis_grad [T][C][B] c64, gain_grad [A] c64 or None) of a loss with dL/dimages = image_grad.
 
     ``weight_sum`` [T*C] float32: the forward call's weight sums (skips
     counting them again). With FP16/BF16 ``vis`` (and ``vis_scale``) the
-    gradient is with respect to the dequantised visibilities. ``phase_lm`` and
-    ``cable_m`` must be those of the forward call.
+    gradient is with respect to the dequantised visibilities. ``phase_lm``,
+    ``cable_m`` and ``reproject`` must be those of the forward call.
     """
     lib = load_library()
     p = make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, weighting, norm, gains, chunk_images,
-                     phase_lm=phase_lm, cable_m=cable_m)
+                     phase_lm=phase_lm, cable_m=cable_m, reproject=reproject)
     inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains, cable_m)
     n_img, M = p.n_time * p.n_chan, p.out_n
     T, C, B = p.n_time, p.n_chan, p.n_bl
@@ -386,31 +390,33 @@ class BlinkImage(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, vis, gains, uvw_m, freq_hz, ant1, ant2, flags, grid_n, pixscale, out_n,
-                weighting, norm, phase_lm=(0.0, 0.0), cable_m=None):
+                weighting, norm, phase_lm=(0.0, 0.0), cable_m=None, reproject=False):
         wsum = torch.empty((vis.shape[0] * vis.shape[1],), dtype=torch.float32, device=vis.device)
         img = image_batch(vis, uvw_m, freq_hz, grid_n=grid_n, pixscale=pixscale, out_n=out_n,
                           weighting=weighting, norm=norm, flags=flags, ant1=ant1, ant2=ant2,
-                          gains=gains, weight_sum=wsum, phase_lm=phase_lm, cable_m=cable_m)
+                          gains=gains, weight_sum=wsum, phase_lm=phase_lm, cable_m=cable_m,
+                          reproject=reproject)
         ctx.save_for_backward(vis, gains, uvw_m, freq_hz, ant1, ant2, flags, wsum, cable_m)
-        ctx.cfg = (grid_n, pixscale, out_n, weighting, norm, phase_lm)
+        ctx.cfg = (grid_n, pixscale, out_n, weighting, norm, phase_lm, reproject)
         return img
 
     @staticmethod
     def backward(ctx, grad_images):
         vis, gains, uvw_m, freq_hz, ant1, ant2, flags, wsum, cable_m = ctx.saved_tensors
-        grid_n, pixscale, out_n, weighting, norm, phase_lm = ctx.cfg
+        grid_n, pixscale, out_n, weighting, norm, phase_lm, reproject = ctx.cfg
         vg, gg = degrid_adjoint(grad_images.contiguous().float(), vis, uvw_m, freq_hz,
                                 grid_n=grid_n, pixscale=pixscale, out_n=out_n,
                                 weighting=weighting, norm=norm, flags=flags, ant1=ant1,
                                 ant2=ant2, gains=gains,
                                 want_gain_grad=gains is not None and ctx.needs_input_grad[1],
-                                weight_sum=wsum, phase_lm=phase_lm, cable_m=cable_m)
+                                weight_sum=wsum, phase_lm=phase_lm, cable_m=cable_m, reproject=reproject)
         return (vg if ctx.needs_input_grad[0] else None, gg, None, None, None, None, None,
-                None, None, None, None, None, None, None)
+                None, None, None, None, None, None, None, None)
 
 
 def blink_image(vis, gains, uvw_m, freq_hz, ant1, ant2, *, grid_n, pixscale, out_n=None,
-                weighting=NATURAL, norm=NORM_WEIGHTS, flags=None, phase_lm=(0.0, 0.0), cable_m=None):
+                weighting=NATURAL, norm=NORM_WEIGHTS, flags=None, phase_lm=(0.0, 0.0), cable_m=None,
+                reproject=False):
     """Functional form of BlinkImage."""
     return BlinkImage.apply(vis, gains, uvw_m, freq_hz, ant1, ant2, flags, grid_n, pixscale,
-                            grid_n if out_n is None else out_n, weighting, norm, phase_lm, cable_m)
+                            grid_n if out_n is None else out_n, weighting, norm, phase_lm, cable_m, reproject)

@@ -169,6 +169,7 @@ blink_status validate_problem(const blink_problem* p, int call) {
     return BLINK_E_ARG;
   if (p->rows_wg < 0) return BLINK_E_ARG;
   if (p->kernel_support < 0 || p->kernel_support > KB_MAX_SUPPORT) return BLINK_E_ARG;
+  if (p->reproject != 0 && p->reproject != 1) return BLINK_E_ARG;
   if (!isfinite(p->phase_l) || !isfinite(p->phase_m) ||
       !(p->phase_l * p->phase_l + p->phase_m * p->phase_m < 1.0))
     return BLINK_E_ARG;
@@ -287,6 +288,16 @@ int run_sort(const blink_problem* p, const blink_inputs* in, const Work& w, hipS
     s.ant1 = in->ant1;
     s.ant2 = in->ant2;
     s.n_ant = p->n_ant;
+  }
+  if (p->reproject && rotates(p)) {
+    // axes of the tangent plane at s0 (the zenith frame's east and north
+    // axes carried by the smallest rotation that takes zenith to s0)
+    const double l0 = p->phase_l, m0 = p->phase_m;
+    const double n0 = sqrt(1.0 - l0 * l0 - m0 * m0);
+    const double k = 1.0 / (1.0 + n0);
+    s.proj = 1;
+    s.eu[0] = n0 + m0 * m0 * k; s.eu[1] = -l0 * m0 * k; s.eu[2] = -l0;
+    s.ev[0] = -l0 * m0 * k; s.ev[1] = n0 + l0 * l0 * k; s.ev[2] = -m0;
   }
   const bool small = B > 0 && B <= SORT_RUN;
   const bool bounds = img && small && p->n_chan == 1;

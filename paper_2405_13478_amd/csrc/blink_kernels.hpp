@@ -63,6 +63,8 @@ struct SortArgs {
   int* perm;                     // [T][B] baseline index in the same order
   double* sd;                    // [T][B] delay in the same order, or null (no rotation)
   double pl, pm, pn1;            // phase centre l0, m0 and n0 - 1
+  int proj;                      // 1: grid the baselines re-projected onto the new centre's plane
+  double eu[3], ev[3];           // with proj: u' = eu . (u, v, w), v' = ev . (u, v, w)
   const double* cable;           // [A] electrical cable lengths (m) or null
   const int* ant1;               // [B] (with cable lengths)
   const int* ant2;               // [B]
@@ -76,6 +78,20 @@ struct SortArgs {
   int* bnd;                      // [T][N + 2]
   int* ncz;                      // [T]
 };
+
+// The (u, v) in metres that the imager grids for baseline o of the flat
+// [T][B] layout: the baseline's own, or its components along the new
+// centre's tangent-plane axes when re-projecting.
+__device__ __forceinline__ void plane_uv(const SortArgs& a, size_t o, double& u, double& v) {
+  const double* b = a.uvw + o * 3;
+  if (a.proj) {
+    u = a.eu[0] * b[0] + a.eu[1] * b[1] + a.eu[2] * b[2];
+    v = a.ev[0] * b[0] + a.ev[1] * b[1] + a.ev[2] * b[2];
+  } else {
+    u = b[0];
+    v = b[1];
+  }
+}
 
 // u l0 + v m0 + w (n0 - 1): the path difference (metres) between the new
 // phase centre and zenith for baseline uvw.
@@ -120,8 +136,8 @@ __global__ void __launch_bounds__(1024) k_sort_run(SortArgs a) {
     if (i < len) {
       const int b = base + i;
       const size_t o = (size_t)t * a.B + b;
-      const double u = a.uvw[o * 3 + 0];
-      const double v = a.uvw[o * 3 + 1];
+      double u, v;
+      plane_uv(a, o, u, v);
       const bool flagged = a.flags != nullptr && a.flags[o] != 0;
       unf += flagged ? 0 : 1;
       if (!flagged && isfinite(u) && isfinite(v)) k = order_key(u);
@@ -207,8 +223,8 @@ __global__ void __launch_bounds__(1024) k_sort_small(SortArgs a) {
     unsigned long long k = KEY_MAX;
     int id = 0x7fffffff;
     if (i < a.B) {
-      const double u = a.uvw[(tb + i) * 3 + 0];
-      const double v = a.uvw[(tb + i) * 3 + 1];
+      double u, v;
+      plane_uv(a, tb + i, u, v);
       const bool flagged = a.flags != nullptr && a.flags[tb + i] != 0;
       unf += flagged ? 0 : 1;
       if (!flagged && isfinite(u) && isfinite(v)) { k = order_key(u); ++val; }
@@ -240,8 +256,9 @@ __global__ void __launch_bounds__(1024) k_sort_small(SortArgs a) {
   double vm = 0.0;
   for (int j = threadIdx.x; j < a.B; j += blockDim.x) {
     const int b = si[j];
-    const double v = a.uvw[(tb + b) * 3 + 1];
-    a.su[tb + j] = a.uvw[(tb + b) * 3 + 0];
+    double u, v;
+    plane_uv(a, tb + b, u, v);
+    a.su[tb + j] = u;
     a.sv[tb + j] = v;
     if (a.sd != nullptr) a.sd[tb + j] = baseline_delay(a, tb, b);
     a.perm[tb + j] = b;
@@ -263,7 +280,9 @@ __global__ void __launch_bounds__(1024) k_sort_small(SortArgs a) {
     const double s = cells_per_metre(a.freq[0], a.ndx);
     const int H = a.N / 2;
     auto ucol = [&](int j) -> int {
-      const double x = rint(a.uvw[(tb + si[j]) * 3 + 0] * s);
+      double u, v;
+      plane_uv(a, tb + si[j], u, v);                          // the u of sorted position j
+      const double x = rint(u * s);
       return (int)fmin(fmax(x, (double)-H), (double)H);
     };
     image_bounds(ucol, s_val, a.N, a.kw, a.bnd + (size_t)t * (a.N + 2), a.ncz + t);
@@ -307,8 +326,10 @@ __global__ void __launch_bounds__(256) k_sort_finish(SortArgs a, int src) {
   const size_t tb = (size_t)t * a.B;
   const unsigned long long k = a.key[src][tb + j];
   const int b = a.idx[src][tb + j];
-  a.su[tb + j] = a.uvw[(tb + b) * 3 + 0];
-  a.sv[tb + j] = a.uvw[(tb + b) * 3 + 1];
+  double u, v;
+  plane_uv(a, tb + b, u, v);
+  a.su[tb + j] = u;
+  a.sv[tb + j] = v;
   if (a.sd != nullptr) a.sd[tb + j] = baseline_delay(a, tb, b);
   a.perm[tb + j] = b;
   const bool valid = k != KEY_MAX;

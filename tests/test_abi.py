@@ -84,6 +84,7 @@ def _image(lib, p, inp, images=FAKE, ws=None, nbytes=0):
     (dict(kernel_support=4, kernel_beta=float("inf")), E_ARG),
     (dict(phase_l=float("nan")), E_ARG), (dict(phase_l=0.8, phase_m=0.6), E_ARG),   # needs l^2 + m^2 < 1
     (dict(phase_m=float("inf")), E_ARG),
+    (dict(phase_l=0.1, reproject=2), E_ARG), (dict(reproject=-1), E_ARG),
 ])
 def test_problem_validation(lib, kw, code):
     assert _image(lib, _prob(**kw), _inputs()) == code
@@ -214,6 +215,13 @@ def test_correlate_validation(lib):
     assert c(FAKE, 1, 1, 8, 32, None, None, None) == E_ARG
     assert c(ctypes.c_void_p(0x100008), 1, 1, 8, 32, FAKE, None, None) == E_ARG   # misaligned
     assert c(None, 0, 4, 8, 32, None, None, None) == E_OK                # empty
+
+
+def test_problem_struct_layout_matches_the_header():
+    # the binding's ctypes layout of blink_problem: 8-byte doubles aligned, the
+    # trailing reproject flag after phase_m, padded to a multiple of 8
+    assert B.Problem.reproject.offset == B.Problem.phase_m.offset + 8
+    assert ctypes.sizeof(B.Problem) == B.Problem.reproject.offset + 8
 
 
 def test_phase_rotation_adjoint_passes_validation(lib):
