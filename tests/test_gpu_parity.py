@@ -179,7 +179,42 @@ def test_ragged_batch_equals_per_image_calls():
             assert torch.equal(one[0], full[t * w.n_chan + ch])
 
 
+def test_ragged_batch_matches_oracle_on_every_image():
+    # 8 timesteps x 4 channels of the all-sky station, 2-10% of the baselines
+    # flagged differently in every timestep: each of the 32 images of one call
+    # against the oracle
+    w = synth.station_allsky(n_time=8, n_chan=4)
+    d = inputs(w)
+    nf = w.flags.sum(axis=1)
+    assert len(set(nf.tolist())) > 1
+    img, ws = run_image(w, d)
+    ref, W = oracle_images(w, d["vis"].cpu().numpy(), range(w.n_img))
+    errs = per_image_rel_l2(img.cpu().numpy(), ref)
+    print(f"  ragged 32 images: max rel-L2 {max(errs):.2e}", flush=True)
+    assert max(errs) <= REL_L2_FP32
+    assert np.array_equal(ws.cpu().numpy(), np.asarray(W, dtype=np.float32))
+
+
 # ------------------------------------------------------------------ precision form
+@pytest.mark.parametrize("dt", [torch.float16, torch.bfloat16])
+def test_half_storage_parity_2048(dt):
+    # the precision workload's own size (2048^2, uniform), one image per format
+    w = synth.precision_station(n_time=1, n_chan=1)
+    d = inputs(w)
+    q, sig = synth.quantize_vis(d["vis"], dt)
+    img, _ = run_image(w, dict(d, vis=q, vis_scale=sig))
+    qn = q.cpu()
+    if dt == torch.bfloat16:
+        bits = qn.view(torch.int16).numpy().view(np.uint16)
+        re, im = bits[..., 0], bits[..., 1]
+    else:
+        re, im = qn[..., 0].numpy(), qn[..., 1].numpy()
+    deq = oracle.dequantize(re, im, sig.cpu().numpy()[None, :, None].astype(np.float64))
+    ref, _ = oracle_images(w, deq, [0])
+    err = per_image_rel_l2(img.cpu().numpy(), ref)[0]
+    print(f"  {dt} at 2048^2: rel-L2 vs dequantised oracle {err:.2e}", flush=True)
+    assert err <= REL_L2_FP32
+
 @pytest.mark.parametrize("dt", [torch.float16, torch.bfloat16])
 def test_half_storage_parity(dt):
     w = synth.precision_station(n_time=1, n_chan=2)
