@@ -43,6 +43,9 @@ bool n_supported(int n) {
 inline size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int KB_MAX_SUPPORT = 16;
+// sharpest accepted shape: I0(beta) stays within FP32 range where the weights
+// come from cyl_bessel_i0f
+constexpr double KB_MAX_BETA = 80.0;
 // supports up to this take the kernel-gridding form with fewer row-weight registers
 constexpr int KB_SMALL_SUPPORT = 8;
 
@@ -70,21 +73,53 @@ double bessel_i0(double x) {
   return sum;
 }
 
-// Coefficients c_k = (beta^2 / 4)^k / ((k!)^2 I0(beta)) of the Kaiser-Bessel
-// weight as a power series in w = 1 - (2d/W)^2; the series form is switched on
-// when the terms beyond the kept ones add less than 1e-8 at w = 1 (all terms
-// are positive and, past k = beta / 2, shrink by the ratio q below).
-void kb_series(double beta, ImgArgs* a) {
-  const double q4 = 0.25 * beta * beta;
-  const double i0 = bessel_i0(beta);
-  double c = 1.0 / i0;
-  for (int k = 0; k < KB_POLY_TERMS; ++k) {
-    if (k > 0) c *= q4 / ((double)k * k);
-    a->kpoly[k] = (float)c;
+// Polynomial of the Kaiser-Bessel weight in s = 2w - 1, w = 1 - (2d/W)^2
+// (see kb_weight): C interpolated at KB_CHEB_NODES Chebyshev points of s, the
+// Chebyshev series truncated after the first degree D whose dropped terms sum
+// below 2e-8 in magnitude, then rewritten in powers of s (double) and rounded
+// once to float (kpoly[k] of s^k, zeros above D). Switched off when no D below
+// KB_POLY_TERMS suffices or the interpolant's last terms have not decayed.
+constexpr int KB_CHEB_NODES = 40;
+
+void kb_poly(double beta, ImgArgs* a) {
+  const int n = KB_CHEB_NODES;
+  const double pi = 3.14159265358979323846;
+  const double inv = 1.0 / bessel_i0(beta);
+  double g[KB_CHEB_NODES], c[KB_CHEB_NODES];
+  for (int i = 0; i < n; ++i) {
+    const double s = cos(pi * (i + 0.5) / n);
+    g[i] = bessel_i0(beta * sqrt(0.5 * (1.0 + s))) * inv;
   }
-  const double next = c * q4 / ((double)KB_POLY_TERMS * KB_POLY_TERMS);
-  const double q = q4 / ((double)(KB_POLY_TERMS + 1) * (KB_POLY_TERMS + 1));
-  a->kpoly_on = q < 0.5 && next / (1.0 - q) < 1e-8 ? 1 : 0;
+  for (int j = 0; j < n; ++j) {
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc += g[i] * cos(pi * j * (i + 0.5) / n);
+    c[j] = acc * (j == 0 ? 1.0 : 2.0) / n;
+  }
+  a->kpoly_on = 0;
+  if (fabs(c[n - 1]) + fabs(c[n - 2]) > 1e-12) return;       // not resolved by n nodes
+  int deg = -1;
+  double tail = 0.0;
+  for (int j = n - 1; j >= 0; --j) {                         // smallest D with sum_{j > D} |c_j| < 2e-8
+    if (tail + fabs(c[j]) >= 2e-8) { deg = j; break; }
+    tail += fabs(c[j]);
+  }
+  if (deg < 0) deg = 0;
+  if (deg > KB_POLY_TERMS - 1) return;
+  // sum_j c_j T_j(s) in powers of s: T_0 = 1, T_1 = s, T_{j+1} = 2 s T_j - T_{j-1}
+  double m[KB_POLY_TERMS] = {0.0}, t0[KB_POLY_TERMS] = {0.0}, t1[KB_POLY_TERMS] = {0.0};
+  t0[0] = 1.0;
+  t1[1] = 1.0;
+  m[0] = c[0];
+  if (deg >= 1) m[1] += c[1];
+  for (int j = 2; j <= deg; ++j) {
+    double t2[KB_POLY_TERMS] = {0.0};
+    for (int k = 0; k <= j; ++k) t2[k] = (k > 0 ? 2.0 * t1[k - 1] : 0.0) - t0[k];
+    for (int k = 0; k <= j; ++k) m[k] += c[j] * t2[k];
+    for (int k = 0; k < KB_POLY_TERMS; ++k) { t0[k] = t1[k]; t1[k] = t2[k]; }
+  }
+  for (int k = 0; k < KB_POLY_TERMS; ++k) a->kpoly[k] = k <= deg ? (float)m[k] : 0.0f;
+  a->kpoly_deg = deg;
+  a->kpoly_on = 1;
 }
 
 struct Work {
@@ -174,7 +209,7 @@ blink_status validate_problem(const blink_problem* p, int call) {
       !(p->phase_l * p->phase_l + p->phase_m * p->phase_m < 1.0))
     return BLINK_E_ARG;
   if (p->kernel_support > 0) {
-    if (!isfinite(p->kernel_beta)) return BLINK_E_ARG;
+    if (!isfinite(p->kernel_beta) || p->kernel_beta > KB_MAX_BETA) return BLINK_E_ARG;
     if (p->kernel_beta < 0 && kb_default_beta(p->kernel_support) < 0) return BLINK_E_ARG;
   }
   if (call < BLINK_CALL_GRID || call > BLINK_CALL_ADJOINT) return BLINK_E_ARG;
@@ -370,7 +405,7 @@ ImgArgs make_args(const blink_problem* p, const blink_inputs* in, const Work& w)
     a.kinv = (float)(1.0 / bessel_i0(beta));
     a.ktaper0 = (float)(beta > 0 ? sinh(beta) / beta : 1.0);
     a.k2w = (float)(2.0 / a.kw);
-    kb_series(beta, &a);
+    kb_poly(beta, &a);
   }
   return a;
 }

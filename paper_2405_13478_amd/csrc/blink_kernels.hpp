@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(256) k_sort_finish(SortArgs a, int src) {
 }
 
 // ============================================================== cell bounds
-// terms of the power series of the Kaiser-Bessel weight (see kb_weight)
+// largest number of coefficients of the Kaiser-Bessel weight's polynomial (see kb_weight)
 constexpr int KB_POLY_TERMS = 25;
 
 struct ImgArgs {
@@ -386,7 +386,8 @@ struct ImgArgs {
   float ktaper0;                // sinh(kbeta) / kbeta: the correction's value at 0 before normalising
   float k2w;                    // 2 / W
   int kpoly_on;                 // 1: weights from kpoly, 0: from cyl_bessel_i0f
-  float kpoly[KB_POLY_TERMS];   // C as a power series in 1 - (2d/W)^2 (see kb_weight)
+  int kpoly_deg;                // degree D of that polynomial (<= KB_POLY_TERMS - 1)
+  float kpoly[KB_POLY_TERMS];   // its coefficients in s = 1 - 2 (2d/W)^2, kpoly[k] of s^k, 0 above D
   // kernel gridding with uniform weighting: [chunk][B] per sorted entry, the
   // kept entries (direct and mirrored) at its nearest cell; null otherwise
   int* kdens;
@@ -665,22 +666,34 @@ __device__ __forceinline__ void grid_steps(const ImgArgs& a, const ColSpan& c, i
 
 // ------------------------------------------------------------- kernel gridding
 // Kaiser-Bessel weight C(d) = I0(beta sqrt(1 - (2d/W)^2)) / I0(beta), |d| <= W/2.
-// I0(beta sqrt(w)) = sum_k (beta^2 w / 4)^k / (k!)^2 is a power series in
-// w = 1 - (2d/W)^2 in [0, 1] with positive coefficients, so Horner's rule in
-// FP32 evaluates it without cancellation; the host supplies the first
-// KB_POLY_TERMS coefficients divided by I0(beta) when the remaining tail is
-// below 1e-8 (beta up to about 20, which covers the default shape up to
-// W = 8), and the weights otherwise come from cyl_bessel_i0f.
+// I0(beta sqrt(w)) is an entire function of w = 1 - (2d/W)^2 in [0, 1], so a
+// polynomial of low degree in s = 2w - 1 in [-1, 1] matches it closely: the
+// host interpolates C at Chebyshev points of s and keeps the shortest
+// truncation whose dropped Chebyshev terms sum below 2e-8 (degree 11 at
+// W = 6 with the default shape). Its coefficients in powers of s are the
+// function's expansion around w = 1/2, all positive and summing to about 1,
+// so Horner's rule in FP32 loses no accuracy to cancellation. The degree
+// picks one of three fixed-length forms (12, 16 or 25 coefficients, zeros
+// above the degree), so that the coefficients stay in scalar registers and
+// the loops unroll. Beyond 25 coefficients (beta above about 70) the weights
+// come from cyl_bessel_i0f.
+template <int TERMS>
+__device__ __forceinline__ float kb_horner(float s, const float* c) {
+  float p = c[TERMS - 1];
+#pragma unroll
+  for (int k = TERMS - 2; k >= 0; --k) p = fmaf(p, s, c[k]);
+  return p;
+}
+
 __device__ __forceinline__ float kb_weight(float d, const ImgArgs& a) {
   const float t = d * a.k2w;
-  const float w = fmaxf(0.0f, fmaf(-t, t, 1.0f));
   if (a.kpoly_on) {
-    float p = a.kpoly[KB_POLY_TERMS - 1];
-#pragma unroll
-    for (int k = KB_POLY_TERMS - 2; k >= 0; --k) p = fmaf(p, w, a.kpoly[k]);
-    return p;
+    const float s = fmaxf(-1.0f, fmaf(-2.0f * t, t, 1.0f));
+    if (a.kpoly_deg < 12) return kb_horner<12>(s, a.kpoly);
+    if (a.kpoly_deg < 16) return kb_horner<16>(s, a.kpoly);
+    return kb_horner<KB_POLY_TERMS>(s, a.kpoly);
   }
-  return cyl_bessel_i0f(a.kbeta * sqrtf(w)) * a.kinv;
+  return cyl_bessel_i0f(a.kbeta * sqrtf(fmaxf(0.0f, fmaf(-t, t, 1.0f)))) * a.kinv;
 }
 
 // Normalised transform of the continuous kernel at xi cycles per cell:

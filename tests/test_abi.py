@@ -82,6 +82,7 @@ def _image(lib, p, inp, images=FAKE, ws=None, nbytes=0):
     (dict(kernel_support=1, kernel_beta=-1.0), E_ARG),        # default shape needs W >= 2
     (dict(kernel_support=4, kernel_beta=float("nan")), E_ARG),
     (dict(kernel_support=4, kernel_beta=float("inf")), E_ARG),
+    (dict(kernel_support=4, kernel_beta=80.5), E_ARG),              # I0(beta) beyond FP32
     (dict(phase_l=float("nan")), E_ARG), (dict(phase_l=0.8, phase_m=0.6), E_ARG),   # needs l^2 + m^2 < 1
     (dict(phase_m=float("inf")), E_ARG),
     (dict(phase_l=0.1, reproject=2), E_ARG), (dict(reproject=-1), E_ARG),

@@ -46,8 +46,7 @@ def _run(w, d, support, beta=-1.0, weighting=0, **kw):
     return img, ws
 
 
-# W <= 8 takes the weight's power series and the short footprint form; W = 12
-# the Bessel routine and the long form
+# W <= 8 takes the short footprint form, W = 12 the long one
 @pytest.mark.parametrize("name,support", [("plain128", 4), ("plain128", 6), ("plain128", 12),
                                           ("allsky180", 4), ("wide512", 6), ("wide512", 8)])
 def test_kernel_image_parity(name, support):
@@ -71,6 +70,18 @@ def test_explicit_beta_and_unnormalised():
     ref, _ = kg.image_batch_conv(d["vis"].cpu().numpy(), w.uvw_m, w.freq_hz, w.grid_n, w.pixscale,
                                  w.out_n, 0, 5, 7.5, w.flags)
     assert max(per_image_rel_l2(img.cpu().numpy(), ref)) <= REL_L2_FP32
+
+
+def test_very_sharp_kernel_takes_the_bessel_routine():
+    # beta = 80 (the largest accepted) needs more polynomial terms than the
+    # library keeps, so the weights come from cyl_bessel_i0f: same parity bar
+    w = _case("plain128")
+    d = inputs(w)
+    img, ws = _run(w, d, 12, beta=80.0)
+    ref, W = kg.image_batch_conv(d["vis"].cpu().numpy(), w.uvw_m, w.freq_hz, w.grid_n, w.pixscale,
+                                 w.out_n, w.norm, 12, 80.0, w.flags)
+    assert max(per_image_rel_l2(img.cpu().numpy(), ref)) <= REL_L2_FP32
+    assert np.allclose(ws.cpu().numpy(), W, rtol=2e-6, atol=0)
 
 
 def test_box_kernel_of_width_one_grids_like_nearest_cell():
