@@ -425,12 +425,23 @@ void launch_cols_image(ImgArgs& a, int n, hipStream_t st) {
   hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, UNI, CPW>), g1, dim3(C_::THREADS), C_::grid_lds_bytes(UNI), st, a);
 }
 
+// the cutout M = N/2 (half of the grid's field) gets the form with the
+// cutout fixed at compile time
+template <int N>
+constexpr bool half_cutout_form() { return N >= 512; }
+
 template <int N, int CPW, bool UNI>
 void launch_cols_half(ImgArgs& a, int n, hipStream_t st) {
   using C_ = ColsHalf<N, CPW, UNI>;
   a.ntiles = (int)cdiv(N / 2, CPW);
   a.wtiles = N / 2;                       // one partial per column
   const dim3 g1((unsigned)(cdiv(n, 8) * 8LL * a.ntiles));
+  if constexpr (half_cutout_form<N>()) {
+    if (a.M == N / 2) {
+      hipLaunchKernelGGL((k_grid_cols_half<N, CPW, UNI, N / 4>), g1, dim3(C_::THREADS), C_::LDS, st, a);
+      return;
+    }
+  }
   hipLaunchKernelGGL((k_grid_cols_half<N, CPW, UNI>), g1, dim3(C_::THREADS), C_::LDS, st, a);
 }
 
@@ -485,6 +496,13 @@ void launch_rows(const blink_problem* p, ImgArgs& a, long long nwg, size_t lds, 
   if constexpr (rows_half<N>()) {
     if constexpr (blocks_aligned(N) && N <= ROWS_BLOCK_STORE_MAX_N) {
       if ((p->out_n / 2) % WAVE == 0) {
+        if constexpr (half_cutout_form<N>()) {
+          if (p->out_n == N / 2) {
+            hipLaunchKernelGGL((k_rows_half<N, true, KB, N / 4>), dim3((unsigned)nwg), dim3(RowsHalf<N>::THREADS),
+                               lds, st, a);
+            return;
+          }
+        }
         hipLaunchKernelGGL((k_rows_half<N, true, KB>), dim3((unsigned)nwg), dim3(RowsHalf<N>::THREADS), lds, st, a);
         return;
       }

@@ -1170,7 +1170,10 @@ __device__ __forceinline__ void grid_col_half(const ImgArgs& a, const ColSpan& c
 }
 
 // Same tiling, XCD mapping and outputs as k_grid_cols<N, MODE_IMAGE, UNI, CPW>.
-template <int N, int CPW, bool UNI>
+// HMC > 0: the cutout half-width M/2 fixed at compile time (M = N/2 takes
+// HMC = N/4), so that the last stage computes only the outputs it stores and
+// the cutout tests vanish; 0: read from the arguments.
+template <int N, int CPW, bool UNI, int HMC = 0>
 __global__ void __launch_bounds__((ColsHalf<N, CPW, UNI>::THREADS)) k_grid_cols_half(ImgArgs a) {
   extern __shared__ float4 lds_raw[];
   using C_ = ColsHalf<N, CPW, UNI>;
@@ -1236,7 +1239,7 @@ __global__ void __launch_bounds__((ColsHalf<N, CPW, UNI>::THREADS)) k_grid_cols_
       // rows of the cutout straight from the last stage: output row m holds
       // v-frequency q = (m - M/2) mod N
       float2* dst = a.half + ((size_t)li * H + col) * a.M;
-      const int hm = a.M / 2;
+      const int hm = HMC > 0 ? HMC : a.M / 2;
       wave_fft_half_emit<N, +1, ZB>(hbuf, lane, tw, in, [&](auto qb, float2 v) {
         cutout_block<N, decltype(qb)::value>(lane, hm, [&](unsigned m) { store_at(dst, m, v); });
       });
@@ -1411,7 +1414,8 @@ struct RowsHalf {
   static constexpr size_t LDS = (size_t)(PPW * STRIDE + TW) * sizeof(float2);
 };
 
-template <int N, bool AL, bool KB>
+// HMC > 0: the cutout half-width fixed at compile time (see k_grid_cols_half).
+template <int N, bool AL, bool KB, int HMC = 0>
 __global__ void __launch_bounds__(RowsHalf<N>::THREADS) k_rows_half(ImgArgs a) {
   static_assert(!AL || blocks_aligned(N), "aligned cutout needs aligned blocks");
   extern __shared__ float4 lds_raw[];
@@ -1517,8 +1521,9 @@ __global__ void __launch_bounds__(RowsHalf<N>::THREADS) k_rows_half(ImgArgs a) {
           s0 *= lcorr[2 * pair];
           s1 *= lcorr[2 * pair + 1];
         }
-        int hm = M / 2;
-        asm volatile("" : "+s"(hm));   // block tests stay inside the loop (hoisted they spill)
+        int hm = HMC > 0 ? HMC : M / 2;
+        // block tests stay inside the loop (hoisted they spill)
+        if constexpr (HMC == 0) asm volatile("" : "+s"(hm));
         // image columns of the cutout straight from the last stage: column l
         // holds u-frequency q = (l - M/2) mod N; row 2p is Re z, row 2p+1 is Im z
         wave_fft_half_emit<N, +1, ZB>(z, lane_i, tw, in, [&](auto qb, float2 v) {
