@@ -363,8 +363,8 @@ def bench_images(args, np, torch, blink, synth, dev):
                           for b in range(min(args.steps, n_batches))])
     unflagged = (B if w.flags is None else
                  float(np.mean([(w.flags[t] == 0).sum() for t in range(min(args.steps, n_batches) * TT)])))
-    if ksup:   # a kernel reaches up to W/2 + 1 columns beyond the outermost baseline
-        ncz = np.minimum(ncz + ksup // 2 + 1, H)
+    if ksup:   # a kernel reaches up to floor(W/2 + 1/2) columns beyond the outermost baseline's
+        ncz = np.minimum(ncz + (ksup + 1) // 2, H)
     ncz_mean = float(ncz.mean())
 
     def measure(v, scale, vbytes):

@@ -198,8 +198,9 @@ __device__ __forceinline__ void image_bounds(UCol&& ucol, int nv, int N, int kw,
     for (int c = clast + 1 + (int)threadIdx.x; c <= H + 1; c += blockDim.x) bnd[c + H] = nv;
   }
   // every entry lies in a column |c| <= max(|first|, |last|) of the sorted order;
-  // a gridding kernel reaches at most W/2 + 1 columns further
-  const int reach = kw > 0 ? kw / 2 + 1 : 0;
+  // a gridding kernel reaches columns c with |c - x_u| <= W/2, i.e. at most
+  // floor(W/2 + 1/2) columns beyond the entry's nearest one
+  const int reach = kw > 0 ? (kw + 1) / 2 : 0;
   if (threadIdx.x == 0) *ncz = nv == 0 ? 0 : min(H, max(clast, -ucol(0)) + 1 + reach);
 }
 
@@ -741,7 +742,8 @@ __device__ __forceinline__ void kb_add_rows(float2* buf, int* cnt, int j0, int n
 }
 
 // Kernel gridding of u-cell column c: the span holds the sorted entries whose
-// nearest column lies within W/2 + 1 of c (direct) and of -c (mirror). Each
+// nearest column c' lies within floor(W/2 + 1/2) of c (direct) and of -c
+// (mirror): |c - x_u| <= W/2 and |x_u - c'| <= 1/2 bound |c - c'|. Each
 // direct entry at exact position x adds C(c - x_u) C(j - x_v) V' to the rows j
 // of its footprint, each mirror entry (its conjugate, at -x) adds
 // C(c + x_u) C(j + x_v) conj(V'). One entry per lane per step; its W + 1
@@ -970,7 +972,7 @@ __global__ void __launch_bounds__((Cols<N, CPW>::THREADS)) k_grid_cols(ImgArgs a
   int kept_b = 0, wcontrib = 0;
   if (KB && active && cs != H && cs != -H) {
     const int* bnd = a.bnd + (size_t)img * (N + 2);
-    const int hk = a.kw / 2 + 1;
+    const int hk = (a.kw + 1) / 2;                  // see grid_steps_kb
     auto at = [&](int c) { return bnd[min(max(c, -H), H + 1) + H]; };
     const ColSpan span{at(cs - hk), at(cs + hk + 1), at(-cs - hk), at(-cs + hk + 1)};
     int kd = 0, kc = 0;
