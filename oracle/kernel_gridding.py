@@ -38,6 +38,13 @@ names neither the kernel nor its correction; the readings used here are:
   normalised to c(0) = 1. For the Kaiser-Bessel kernel it has the closed form
   c(xi) = [sinh(z) / z] / [sinh(beta) / beta], z = sqrt(beta^2 - (pi W xi)^2)
   (sin(|z|) / |z| once pi W |xi| > beta), Jackson et al. 1991, IEEE TMI 10, 473.
+* Adjoint (differentiation through kernel gridding): the map V' -> image is
+  linear (weights, W and the correction depend only on geometry and flags),
+  so its adjoint divides the image gradient by the same correction, pads it,
+  scales by 1/W, undoes the shift, applies the forward transform Gh, and
+  degrids: gamma'_b = sum over b's footprint cells of w Gh[cell] plus the
+  conjugate of the same sum over its mirror cells; the gains then follow as
+  for nearest-cell gridding.
 """
 from __future__ import annotations
 
@@ -213,3 +220,69 @@ def direct_fractional_image(vis_prime, xu, xv, keep, grid_n: int, out_n: int):
     ev = np.exp(2j * np.pi * np.outer(xv[k], q) / grid_n)      # [b][m]
     img = 2.0 * np.real(np.einsum("b,bm,bl->ml", vp, ev, eu))
     return img / (2.0 * len(k)) if len(k) else img
+
+
+def adjoint_one_conv(image_grad, vis, u_m, v_m, freq_hz, grid_n, pixscale, norm, support, beta=None,
+                     flagged=None, gains=None, ant1=None, ant2=None, weighting=0, correct=True):
+    """Gradient of sum(image * image_grad) through image_one_conv w.r.t. V (and
+    the gains), convention grad z = dL/dx + i dL/dy: (vis_grad [B], gain_grad
+    [A] or None)."""
+    beta = kb_default_beta(support) if beta is None or beta < 0 else float(beta)
+    n_ = grid_n
+    m_ = image_grad.shape[-1]
+    s = uv_scale(freq_hz, grid_n, pixscale)
+    xu = np.asarray(u_m, dtype=np.float64) * np.float64(s)
+    xv = np.asarray(v_m, dtype=np.float64) * np.float64(s)
+    keep = conv_keep(xu, xv, support, grid_n, flagged)
+    vp = apply_gains(vis, gains, ant1, ant2)
+    om = uniform_weights(xu, xv, keep, grid_n) if weighting == 1 else None
+    _, _, W = grid_conv(vp, xu, xv, keep, grid_n, support, beta, om)
+    g = np.asarray(image_grad, dtype=np.float64)
+    if correct:
+        g = correct_taper(g, grid_n, support, beta)          # a diagonal scaling is its own adjoint
+    P = np.zeros((n_, n_))
+    a = n_ // 2 - m_ // 2
+    P[a:a + m_, a:a + m_] = g
+    if norm == NORM_WEIGHTS:
+        P = P / W if W > 0 else np.zeros_like(P)
+    P = np.roll(P, (-(n_ // 2), -(n_ // 2)), axis=(0, 1))
+    Gh = fft2(P.astype(np.complex128), -1)
+    gp = np.zeros(len(keep), dtype=np.complex128)
+    for b in np.flatnonzero(np.asarray(keep)):
+        iu = footprint(xu[b], support)
+        iv = footprint(xv[b], support)
+        w = np.outer(kb(iv - xv[b], support, beta), kb(iu - xu[b], support, beta))   # [j][i]
+        if om is not None:
+            w = w * om[b]
+        direct = np.sum(w * Gh[np.ix_(np.mod(iv, n_), np.mod(iu, n_))])
+        mirror = np.sum(w * Gh[np.ix_(np.mod(-iv, n_), np.mod(-iu, n_))])
+        gp[b] = direct + np.conj(mirror)
+    if gains is None:
+        return gp, None
+    gg_ = np.asarray(gains).astype(np.complex128)
+    g1 = gg_[np.asarray(ant1)]
+    g2 = gg_[np.asarray(ant2)]
+    v = np.asarray(vis).astype(np.complex128)
+    vgrad = np.conj(g1) * g2 * gp
+    ggrad = np.zeros(len(gg_), dtype=np.complex128)
+    np.add.at(ggrad, np.asarray(ant1), gp * g2 * np.conj(v))
+    np.add.at(ggrad, np.asarray(ant2), np.conj(gp) * g1 * v)
+    return vgrad, ggrad
+
+
+def adjoint_batch_conv(image_grad, vis, uvw_m, freq_hz, grid_n, pixscale, norm, support, beta=None,
+                       flags=None, gains=None, ant1=None, ant2=None, weighting=0):
+    """Adjoint over a cube: image_grad [T*C][M][M] -> (vis_grad [T][C][B], gain_grad [A] or None)."""
+    T, C, B = vis.shape
+    vg = np.zeros((T, C, B), dtype=np.complex128)
+    gg = None if gains is None else np.zeros(len(gains), dtype=np.complex128)
+    for t in range(T):
+        for c in range(C):
+            v_, g_ = adjoint_one_conv(image_grad[t * C + c], vis[t, c], uvw_m[t, :, 0], uvw_m[t, :, 1],
+                                      freq_hz[c], grid_n, pixscale, norm, support, beta,
+                                      None if flags is None else flags[t], gains, ant1, ant2,
+                                      weighting=weighting)
+            vg[t, c] = v_
+            if gg is not None:
+                gg += g_
+    return vg, gg

@@ -221,3 +221,62 @@ def test_uniform_kernel_unit_source_at_centre_peaks_at_one():
     img = r["image"]
     assert abs(img[n // 2, n // 2] - 1.0) <= 1e-12
     assert np.unravel_index(np.argmax(img), img.shape) == (n // 2, n // 2)
+
+
+# ------------------------------------------------------------ adjoint
+def _adj_case(seed, n=32, nb=60, n_ant=8):
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-12, 12, nb)
+    v = rng.uniform(-12, 12, nb)
+    a1 = rng.integers(0, n_ant, nb)
+    a2 = (a1 + 1 + rng.integers(0, n_ant - 1, nb)) % n_ant
+    vis = rng.normal(size=nb) + 1j * rng.normal(size=nb)
+    g = 1 + 0.1 * rng.normal(size=n_ant) + 0.1j * rng.normal(size=n_ant)
+    flagged = rng.random(nb) < 0.1
+    return u, v, vis, a1, a2, g, flagged, n
+
+
+@pytest.mark.parametrize("weighting,norm", [(0, 1), (1, 1), (0, 0)])
+def test_kernel_adjoint_dot_product(weighting, norm):
+    # gains off: the image is linear in V', so <I(V), Ibar> = sum Re(conj(grad) V)
+    u, v, vis, a1, a2, g, flagged, n = _adj_case(40 + weighting + 2 * norm)
+    rng = np.random.default_rng(41)
+    m = 20
+    ibar = rng.normal(size=(m, m))
+    f = oracle.C_LIGHT
+    img = kg.image_one_conv(vis, u, v, f, n, 1.0 / n, m, norm, 6, flagged=flagged, weighting=weighting)["image"]
+    gv, _ = kg.adjoint_one_conv(ibar, vis, u, v, f, n, 1.0 / n, norm, 6, flagged=flagged, weighting=weighting)
+    lhs = np.sum(img * ibar)
+    rhs = np.sum(gv.real * vis.real + gv.imag * vis.imag)
+    assert np.isclose(lhs, rhs, rtol=1e-12, atol=1e-12)
+    assert np.all(gv[flagged] == 0)
+
+
+def test_kernel_adjoint_finite_differences():
+    # FP64 central differences of ||I - T||^2 through kernel gridding with gains
+    u, v, vis, a1, a2, g, flagged, n = _adj_case(44)
+    rng = np.random.default_rng(45)
+    m = 24
+    target = rng.normal(size=(m, m))
+    f = oracle.C_LIGHT
+
+    def loss(vv, gg):
+        img = kg.image_one_conv(vv, u, v, f, n, 1.0 / n, m, 1, 5, 7.0, flagged, gg, a1, a2)["image"]
+        return float(np.sum((img - target) ** 2))
+
+    img = kg.image_one_conv(vis, u, v, f, n, 1.0 / n, m, 1, 5, 7.0, flagged, g, a1, a2)["image"]
+    gv, gg = kg.adjoint_one_conv(2 * (img - target), vis, u, v, f, n, 1.0 / n, 1, 5, 7.0, flagged, g, a1, a2)
+
+    def fd(fun, x, idx, imag):
+        h = 1e-6 * max(1.0, abs(x[idx]))
+        step = 1j * h if imag else h
+        xp = x.copy(); xp[idx] += step
+        xm = x.copy(); xm[idx] -= step
+        return (fun(xp) - fun(xm)) / (2 * h)
+
+    for idx in range(0, len(vis), 7):
+        ref = fd(lambda x: loss(x, g), vis.copy(), idx, False) + 1j * fd(lambda x: loss(x, g), vis.copy(), idx, True)
+        assert abs(gv[idx] - ref) <= 1e-6 * max(1.0, abs(ref)), (idx, gv[idx], ref)
+    for idx in range(len(g)):
+        ref = fd(lambda x: loss(vis, x), g.copy(), idx, False) + 1j * fd(lambda x: loss(vis, x), g.copy(), idx, True)
+        assert abs(gg[idx] - ref) <= 1e-6 * max(1.0, abs(ref)), (idx, gg[idx], ref)
