@@ -71,8 +71,8 @@
  *   (sin(|z|)/|z| where pi W |xi| > beta). Weights are evaluated in FP32 from
  *   the FP64 distances, by a polynomial within 2e-8 of C (plus FP32 rounding)
  *   up to beta of about 70, else by the FP32 Bessel routine; blink_grid
- *   returns counts of contributions per cell.
- *   blink_degrid_adjoint with a kernel returns BLINK_E_UNSUPPORTED.
+ *   returns counts of contributions per cell. blink_degrid_adjoint degrids
+ *   with the same kernel (see there).
  * - Phase rotation (phase_l, phase_m != 0; Sec. 4.2 (iii)): correlation
  *   phases the visibilities to zenith; each V' is multiplied by
  *   exp(+2 pi i (u l0 + v m0 + w (n0 - 1)) nu_c / c0), n0 = sqrt(1 - l0^2 -
@@ -258,8 +258,13 @@ blink_status blink_image_batch_noalloc(const blink_problem* p, const blink_input
  * The map V -> image is linear (W and the counts depend only on geometry and
  * flags), so this is the exact adjoint: zero-pad, 1/W, inverse shift, forward
  * transform, cell weight, gather at +k and -k (degridding), times the
- * conjugate of the rotation / cable factor when one is applied. Nearest-cell
- * gridding only (kernel_support > 0 returns BLINK_E_UNSUPPORTED).
+ * conjugate of the rotation / cable factor when one is applied. With a
+ * gridding kernel (kernel_support > 0) the image gradient is first divided by
+ * the same correction c(q_l/N) c(q_m/N), and the degridding sums, for each
+ * kept baseline, C(i - x_u) C(j - x_v) (times 1/n_b with UNIFORM) over its
+ * footprint cells of the transformed gradient, plus the conjugate of the same
+ * sum over its mirror cells; without weight_sum, W is counted again by the
+ * forward column pass.
  */
 blink_status blink_degrid_adjoint(const blink_problem* p, const blink_inputs* in,
                                   const float* image_grad, const float* weight_sum,

@@ -310,17 +310,20 @@ def fft2d(x, sign=+1, out=None, stream=None):
 def degrid_adjoint(image_grad, vis, uvw_m, freq_hz, *, grid_n, pixscale, out_n=None,
                    weighting=NATURAL, norm=NORM_WEIGHTS, flags=None, ant1=None, ant2=None,
                    gains=None, want_gain_grad=True, chunk_images=0, stream=None, weight_sum=None,
-                   vis_scale=None, phase_lm=(0.0, 0.0), cable_m=None, reproject=False):
+                   vis_scale=None, phase_lm=(0.0, 0.0), cable_m=None, reproject=False,
+                   kernel_support=0, kernel_beta=-1.0):
     """(vis_grad [T][C][B] c64, gain_grad [A] c64 or None) of a loss with dL/dimages = image_grad.
 
     ``weight_sum`` [T*C] float32: the forward call's weight sums (skips
     counting them again). With FP16/BF16 ``vis`` (and ``vis_scale``) the
     gradient is with respect to the dequantised visibilities. ``phase_lm``,
-    ``cable_m`` and ``reproject`` must be those of the forward call.
+    ``cable_m``, ``reproject`` and the gridding kernel must be those of the
+    forward call.
     """
     lib = load_library()
     p = make_problem(vis, uvw_m, freq_hz, grid_n, pixscale, out_n, weighting, norm, gains, chunk_images,
-                     phase_lm=phase_lm, cable_m=cable_m, reproject=reproject)
+                     phase_lm=phase_lm, cable_m=cable_m, reproject=reproject,
+                     kernel_support=kernel_support, kernel_beta=kernel_beta)
     inp, _keep = make_inputs(p, vis, uvw_m, freq_hz, flags, vis_scale, ant1, ant2, gains, cable_m)
     n_img, M = p.n_time * p.n_chan, p.out_n
     T, C, B = p.n_time, p.n_chan, p.n_bl
@@ -390,33 +393,36 @@ class BlinkImage(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, vis, gains, uvw_m, freq_hz, ant1, ant2, flags, grid_n, pixscale, out_n,
-                weighting, norm, phase_lm=(0.0, 0.0), cable_m=None, reproject=False):
+                weighting, norm, phase_lm=(0.0, 0.0), cable_m=None, reproject=False,
+                kernel_support=0, kernel_beta=-1.0):
         wsum = torch.empty((vis.shape[0] * vis.shape[1],), dtype=torch.float32, device=vis.device)
         img = image_batch(vis, uvw_m, freq_hz, grid_n=grid_n, pixscale=pixscale, out_n=out_n,
                           weighting=weighting, norm=norm, flags=flags, ant1=ant1, ant2=ant2,
                           gains=gains, weight_sum=wsum, phase_lm=phase_lm, cable_m=cable_m,
-                          reproject=reproject)
+                          reproject=reproject, kernel_support=kernel_support, kernel_beta=kernel_beta)
         ctx.save_for_backward(vis, gains, uvw_m, freq_hz, ant1, ant2, flags, wsum, cable_m)
-        ctx.cfg = (grid_n, pixscale, out_n, weighting, norm, phase_lm, reproject)
+        ctx.cfg = (grid_n, pixscale, out_n, weighting, norm, phase_lm, reproject, kernel_support, kernel_beta)
         return img
 
     @staticmethod
     def backward(ctx, grad_images):
         vis, gains, uvw_m, freq_hz, ant1, ant2, flags, wsum, cable_m = ctx.saved_tensors
-        grid_n, pixscale, out_n, weighting, norm, phase_lm, reproject = ctx.cfg
+        grid_n, pixscale, out_n, weighting, norm, phase_lm, reproject, ksup, kbeta = ctx.cfg
         vg, gg = degrid_adjoint(grad_images.contiguous().float(), vis, uvw_m, freq_hz,
                                 grid_n=grid_n, pixscale=pixscale, out_n=out_n,
                                 weighting=weighting, norm=norm, flags=flags, ant1=ant1,
                                 ant2=ant2, gains=gains,
                                 want_gain_grad=gains is not None and ctx.needs_input_grad[1],
-                                weight_sum=wsum, phase_lm=phase_lm, cable_m=cable_m, reproject=reproject)
+                                weight_sum=wsum, phase_lm=phase_lm, cable_m=cable_m, reproject=reproject,
+                                kernel_support=ksup, kernel_beta=kbeta)
         return (vg if ctx.needs_input_grad[0] else None, gg, None, None, None, None, None,
-                None, None, None, None, None, None, None, None)
+                None, None, None, None, None, None, None, None, None, None)
 
 
 def blink_image(vis, gains, uvw_m, freq_hz, ant1, ant2, *, grid_n, pixscale, out_n=None,
                 weighting=NATURAL, norm=NORM_WEIGHTS, flags=None, phase_lm=(0.0, 0.0), cable_m=None,
-                reproject=False):
+                reproject=False, kernel_support=0, kernel_beta=-1.0):
     """Functional form of BlinkImage."""
     return BlinkImage.apply(vis, gains, uvw_m, freq_hz, ant1, ant2, flags, grid_n, pixscale,
-                            grid_n if out_n is None else out_n, weighting, norm, phase_lm, cable_m, reproject)
+                            grid_n if out_n is None else out_n, weighting, norm, phase_lm, cable_m, reproject,
+                            kernel_support, kernel_beta)

@@ -140,12 +140,15 @@ struct Work {
   float2* gamma;
   float2* pacc;
   int* kdens;         // kernel gridding with uniform weighting: [chunk][B]
+  float2* gfull;      // adjoint with a gridding kernel: [chunk][N/2][N]
 };
 
 int default_chunk(const blink_problem* p, int call, long long n_img) {
   if (p->chunk_images > 0) return (int)std::min<long long>(p->chunk_images, std::max<long long>(n_img, 1));
   long long per = 1;
   if (call != BLINK_CALL_GRID) per = (long long)(p->grid_n / 2) * p->out_n * 8;
+  // the adjoint with a gridding kernel also keeps every transformed column
+  if (call == BLINK_CALL_ADJOINT && p->kernel_support > 0) per += (long long)(p->grid_n / 2) * p->grid_n * 8;
   long long c = std::max<long long>(1, (long long)CHUNK_TARGET_BYTES / per);
   c = std::min<long long>(c, std::max<long long>(n_img, 1));
   return (int)std::min<long long>(c, MAX_GRID_Y);
@@ -186,8 +189,10 @@ size_t carve(const blink_problem* p, int call, int chunk, char* base, Work* w) {
     x.gamma = (float2*)take((size_t)chunk * B * 8);
     x.pacc = (float2*)take(B * 8);
   }
-  if (call != BLINK_CALL_ADJOINT && p->kernel_support > 0 && p->weighting == BLINK_UNIFORM)
+  if (p->kernel_support > 0 && p->weighting == BLINK_UNIFORM)
     x.kdens = (int*)take((size_t)chunk * B * 4);
+  if (call == BLINK_CALL_ADJOINT && p->kernel_support > 0)
+    x.gfull = (float2*)take((size_t)chunk * (N / 2) * N * 8);
   if (w) *w = x;
   return o;
 }
@@ -221,7 +226,6 @@ blink_status validate_problem(const blink_problem* p, int call) {
   if (T * C > INT32_MAX || T * B > INT32_MAX) return BLINK_E_SIZE;
   if ((double)T * C * B > 9.0e18 || (double)T * C * N * N > 9.0e18) return BLINK_E_SIZE;
   if (!n_supported(p->grid_n)) return BLINK_E_UNSUPPORTED;
-  if (p->kernel_support > 0 && call == BLINK_CALL_ADJOINT) return BLINK_E_UNSUPPORTED;
   return BLINK_OK;
 }
 
@@ -398,12 +402,14 @@ ImgArgs make_args(const blink_problem* p, const blink_inputs* in, const Work& w)
   a.bnd = w.bnd; a.ncz = w.ncz; a.wpart = w.wpart; a.kpart = w.kpart; a.wstride = w.wstride;
   a.half = w.half; a.gamma = w.gamma; a.pacc = w.pacc;
   a.kdens = w.kdens;
+  a.gfull = w.gfull;
   a.kw = p->kernel_support;
   if (a.kw > 0) {
     const double beta = p->kernel_beta < 0 ? kb_default_beta(a.kw) : p->kernel_beta;
     a.kbeta = (float)beta;
     a.kinv = (float)(1.0 / bessel_i0(beta));
-    a.ktaper0 = (float)(beta > 0 ? sinh(beta) / beta : 1.0);
+    a.kbeta_d = beta;
+    a.ktaper0_d = beta > 0 ? sinh(beta) / beta : 1.0;
     a.k2w = (float)(2.0 / a.kw);
     kb_poly(beta, &a);
   }
@@ -607,6 +613,7 @@ template <int N>
 blink_status adjoint_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t st) {
   const long long n_img = (long long)p->n_time * p->n_chan;
   const bool uni = p->weighting == BLINK_UNIFORM;
+  const bool kb = p->kernel_support > 0;
   if (a.gains)
     hipLaunchKernelGGL(k_fill2, dim3(cdiv(a.B, 256)), dim3(256), 0, st, a.pacc, (size_t)a.B);
   a.wtiles = (int)cdiv(N / 2, Cols<N>::CPW);
@@ -614,9 +621,23 @@ blink_status adjoint_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t
   for (long long i0 = 0; i0 < n_img; i0 += chunk) {
     const int n = (int)std::min<long long>(chunk, n_img - i0);
     a.img0 = (int)i0; a.nimg = n;
+    if (a.kdens != nullptr) launch_kb_density<N>(a, n, st);
     // W from the forward call's weight sums when the caller passes them, else
-    // counted again from the sorted lists
-    if (a.wsum_in == nullptr) {
+    // counted again from the sorted lists (with a gridding kernel: by the
+    // forward column pass itself, whose transformed columns the row pass
+    // below then overwrites)
+    if (a.wsum_in == nullptr && kb) {
+      constexpr int CPW = Cols<N>::CPW;
+      a.ntiles = (int)cdiv(N / 2, CPW);
+      const dim3 g1((unsigned)(cdiv(n, 8) * 8LL * a.ntiles));
+      const size_t lds = Cols<N, CPW>::grid_lds_bytes(false);
+      if (p->kernel_support <= KB_SMALL_SUPPORT)
+        hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, false, CPW, true, KB_SMALL_SUPPORT>), g1,
+                           dim3(Cols<N, CPW>::THREADS), lds, st, a);
+      else
+        hipLaunchKernelGGL((k_grid_cols<N, MODE_IMAGE, false, CPW, true, KB_MAX_SUPPORT>), g1,
+                           dim3(Cols<N, CPW>::THREADS), lds, st, a);
+    } else if (a.wsum_in == nullptr) {
       const dim3 gw(cdiv(N / 2, Cols<N>::CPW), n);
       const size_t ldsw = uni ? (size_t)Cols<N>::CPW * N * sizeof(int) : 0;
       if (uni)
@@ -634,11 +655,19 @@ blink_status adjoint_n(const blink_problem* p, ImgArgs a, int chunk, hipStream_t
       hipLaunchKernelGGL(k_fill2, dim3(cdiv((long long)ng, 256)), dim3(256), 0, st, a.gamma, ng);
     a.ntiles = (int)cdiv(N / 2, Cols<N>::CPW);
     const dim3 g1((unsigned)(cdiv(n, 8) * 8LL * a.ntiles));
-    const size_t lds1 = Cols<N>::lds_bytes(uni);
-    if (uni)
+    const size_t lds1 = Cols<N>::lds_bytes(uni && !kb);
+    if (kb) {
+      hipLaunchKernelGGL((k_cols_adj<N, false, true>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
+      const dim3 gd(cdiv(a.B, 256), n);
+      if (p->kernel_support <= KB_SMALL_SUPPORT)
+        hipLaunchKernelGGL((k_degrid_kb<N, KB_SMALL_SUPPORT>), gd, dim3(256), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_degrid_kb<N, KB_MAX_SUPPORT>), gd, dim3(256), 0, st, a);
+    } else if (uni) {
       hipLaunchKernelGGL((k_cols_adj<N, true>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
-    else
+    } else {
       hipLaunchKernelGGL((k_cols_adj<N, false>), g1, dim3(Cols<N>::THREADS), lds1, st, a);
+    }
     if (a.gains)
       hipLaunchKernelGGL(k_gq_reduce, dim3(cdiv(a.B, 64)), dim3(256), 0, st, a);
   }

@@ -379,12 +379,14 @@ struct ImgArgs {
   float2* vis_grad;             // [T][C][B]
   float2* pacc;                 // [B] sum over images of gamma conj(V)
   float2* gain_grad;            // [A]
+  float2* gfull;                // adjoint with a gridding kernel: [chunk][N/2][N] transformed columns
   int n_ant;
   // Kaiser-Bessel gridding kernel (kw = support in cells, 0 = nearest cell)
   int kw;
   float kbeta;                  // shape
   float kinv;                   // 1 / I0(kbeta)
-  float ktaper0;                // sinh(kbeta) / kbeta: the correction's value at 0 before normalising
+  double kbeta_d;               // the shape in double (the correction is formed in double)
+  double ktaper0_d;             // sinh(beta) / beta: the correction's value at 0 before normalising
   float k2w;                    // 2 / W
   int kpoly_on;                 // 1: weights from kpoly, 0: from cyl_bessel_i0f
   int kpoly_deg;                // degree D of that polynomial (<= KB_POLY_TERMS - 1)
@@ -697,16 +699,19 @@ __device__ __forceinline__ float kb_weight(float d, const ImgArgs& a) {
   return cyl_bessel_i0f(a.kbeta * sqrtf(fmaxf(0.0f, fmaf(-t, t, 1.0f)))) * a.kinv;
 }
 
-// Normalised transform of the continuous kernel at xi cycles per cell:
-// [sinh(z)/z] / [sinh(beta)/beta], z = sqrt(beta^2 - (pi W xi)^2) (sin(|z|)/|z|
-// beyond pi W |xi| = beta).
-__device__ __forceinline__ float kb_taper(float xi, const ImgArgs& a) {
-  const float x = 3.14159265358979f * (float)a.kw * xi;
-  const float z2 = a.kbeta * a.kbeta - x * x;
-  float f = 1.0f;
-  if (z2 > 0.0f) { const float z = sqrtf(z2); f = sinhf(z) / z; }
-  else if (z2 < 0.0f) { const float z = sqrtf(-z2); f = sinf(z) / z; }
-  return f / a.ktaper0;
+// Reciprocal of the correction at xi cycles per cell, 1 / c(xi) with
+// c(xi) = [sinh(z)/z] / [sinh(beta)/beta], z = sqrt(beta^2 - (pi W xi)^2)
+// (sin(|z|)/|z| beyond pi W |xi| = beta). Formed in double: near a zero of
+// c (small beta, pixels near the edge of a full-field image) FP32 would lose
+// most of its digits in z.
+__device__ __forceinline__ float kb_inv_taper(double xi, const ImgArgs& a) {
+  const double b = a.kbeta_d;
+  const double x = 3.141592653589793 * (double)a.kw * xi;
+  const double z2 = b * b - x * x;
+  double f = 1.0;
+  if (z2 > 0.0) { const double z = sqrt(z2); f = sinh(z) / z; }
+  else if (z2 < 0.0) { const double z = sqrt(-z2); f = sin(z) / z; }
+  return (float)(a.ktaper0_d / f);
 }
 
 // Adds w[k] v to rows j0 + k, k < nrow, of this column for every active
@@ -1318,7 +1323,7 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows(ImgArgs a) {
   float* lcorr = reinterpret_cast<float*>(lds + PPW * ST + Rows<N>::TW);
   constexpr bool kbon = KB;
   if (kbon)
-    for (int l = threadIdx.x; l < a.M; l += THR) lcorr[l] = 1.0f / kb_taper((float)(l - a.M / 2) / N, a);
+    for (int l = threadIdx.x; l < a.M; l += THR) lcorr[l] = kb_inv_taper((double)(l - a.M / 2) / N, a);
 
   // thread t always serves pair slot t % PPW and columns t / PPW + i * (THR / PPW)
   const int kt = threadIdx.x / PPW, pt = threadIdx.x % PPW;
@@ -1437,7 +1442,7 @@ __global__ void __launch_bounds__(RowsHalf<N>::THREADS) k_rows_half(ImgArgs a) {
   const float2* tw = stage_twiddles<N>(lds + PPW * ST);
   float* lcorr = reinterpret_cast<float*>(lds + PPW * ST + RowsHalf<N>::TW);
   if (KB)
-    for (int l = threadIdx.x; l < a.M; l += THR) lcorr[l] = 1.0f / kb_taper((float)(l - a.M / 2) / N, a);
+    for (int l = threadIdx.x; l < a.M; l += THR) lcorr[l] = kb_inv_taper((double)(l - a.M / 2) / N, a);
 
 #pragma nounroll
   for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
@@ -1951,7 +1956,9 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows_adj(ImgArgs a) {
   const int npair = M / 2;
   const int p0 = blockIdx.x * PPW;
   const int nz = min(H, a.ncz[img]);
-  const float W = a.wsum_in ? a.wsum_in[img] : (float)sum_partials(a.wpart, img, a.wstride, a.wtiles, lane);
+  const float W = a.wsum_in ? a.wsum_in[img]
+                  : a.kw > 0 ? sum_partials_f(a.wpart, img, a.wstride, a.wtiles, lane)
+                             : (float)sum_partials(a.wpart, img, a.wstride, a.wtiles, lane);
   const float scale = a.norm ? (W > 0 ? 1.0f / W : 0.0f) : 1.0f;
   const float2* tw = stage_twiddles<N>(lds + PPW * ST);
   __syncthreads();
@@ -1962,10 +1969,18 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows_adj(ImgArgs a) {
     wave_sync();
     const float* g0 = a.image_grad + ((size_t)img * M + 2 * pair) * M;
     const float* g1 = g0 + M;
+    // with a gridding kernel the forward pass divided pixel (m, l) by
+    // c(q_m / N) c(q_l / N); that diagonal scaling is its own adjoint
+    float s0 = scale, s1 = scale;
+    if (a.kw > 0) {
+      s0 *= kb_inv_taper((double)(2 * pair - M / 2) / N, a);
+      s1 *= kb_inv_taper((double)(2 * pair + 1 - M / 2) / N, a);
+    }
     for (int l = lane; l < M; l += WAVE) {
       int q = l - M / 2;
       q = q < 0 ? q + N : q;
-      z[pad(q)] = make_float2(g0[l] * scale, g1[l] * scale);
+      const float cl = a.kw > 0 ? kb_inv_taper((double)(l - M / 2) / N, a) : 1.0f;
+      z[pad(q)] = make_float2(g0[l] * s0 * cl, g1[l] * s1 * cl);
     }
     wave_sync();
     wave_fft<N, -1>(z, lane, tw);
@@ -1995,7 +2010,9 @@ __global__ void __launch_bounds__(Rows<N>::THREADS) k_rows_adj(ImgArgs a) {
 // (mirror column), both for i_u = 0. Writes vis_grad = conj(g1 conj g2) gamma'
 // and, with gains, gq = gamma' conj(V) for the gain gradient. Same XCD-grouped
 // 1D layout and empty-column skip as the forward kernel.
-template <int N, bool UNI>
+// KBW (adjoint with a gridding kernel): the transformed column is written
+// to a.gfull instead, for k_degrid_kb.
+template <int N, bool UNI, bool KBW = false>
 __global__ void __launch_bounds__(Cols<N>::THREADS) k_cols_adj(ImgArgs a) {
   extern __shared__ float4 lds_raw[];
   constexpr int H = N / 2;
@@ -2052,6 +2069,11 @@ __global__ void __launch_bounds__(Cols<N>::THREADS) k_cols_adj(ImgArgs a) {
   }
   wave_sync();
   wave_fft<N, -1>(buf, lane, tw);
+  if constexpr (KBW) {
+    float2* g = a.gfull + ((size_t)li * H + cs) * N;
+    for (int r = lane; r < N; r += WAVE) g[r] = buf[pad(r)];
+    return;
+  }
   const size_t vb = (size_t)img * a.B;
   // direct entries (and, for column 0, the conjugate entry of the same baseline)
   for (int pass = 0; pass < (cs == 0 ? 1 : 2); ++pass) {
@@ -2090,6 +2112,75 @@ __global__ void __launch_bounds__(Cols<N>::THREADS) k_cols_adj(ImgArgs a) {
         }
       }
     }
+  }
+}
+
+// Adjoint of kernel gridding: gamma'_b = sum over b's footprint cells (j, i)
+// of C(i - x_u) C(j - x_v) G2[j][i], G2 = 2 Gh over the whole plane, taken
+// from the transformed half-spectrum columns B in a.gfull: G2[j][i] = B[j][i]
+// for i > 0 (the row pass packed both Hermitian halves there), B[j][0] +
+// conj(B[-j][0]) for i = 0, conj(G2[-j][-i]) for i < 0. This is the
+// direct-cell sum plus the conjugate of the mirror-cell sum (the gradient
+// image is real, so its transform is Hermitian). One thread per sorted entry
+// of each image of the chunk, summing in a fixed order; then the rotation and
+// gain factors as in k_cols_adj. Uniform weighting divides by the entry's
+// cell occupancy (a.kdens).
+template <int N, int KMAX>
+__global__ void __launch_bounds__(256) k_degrid_kb(ImgArgs a) {
+  constexpr int H = N / 2;
+  const int li = blockIdx.y;
+  const int img = a.img0 + li;
+  const int t = img / a.C, ch = img - t * a.C;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n_valid[t]) return;
+  const size_t tb = (size_t)t * a.B;
+  const double s = cells_per_metre(a.freq[ch], a.ndx);
+  const double hw = 0.5 * a.kw;
+  const double xu = a.su[tb + j] * s, xv = a.sv[tb + j] * s;
+  if (!(ceil(xu - hw) > (double)-H && floor(xu + hw) < (double)H && ceil(xv - hw) > (double)-H &&
+        floor(xv + hw) < (double)H))
+    return;                                          // not kept: its gradient stays zero
+  const int i0 = (int)ceil(xu - hw), ni = (int)floor(xu + hw) - i0 + 1;
+  const int j0 = (int)ceil(xv - hw), nj = (int)floor(xv + hw) - j0 + 1;
+  float wv[KMAX + 1];
+#pragma unroll
+  for (int k = 0; k <= KMAX; ++k) {
+    wv[k] = 0.f;
+    if (k > a.kw) break;
+    if (k < nj) wv[k] = kb_weight((float)((double)(j0 + k) - xv), a);
+  }
+  const float2* G = a.gfull + (size_t)li * H * N;
+  auto at = [&](int r, int c) -> float2 {          // B[r][c], c >= 0
+    return G[(size_t)c * N + (r < 0 ? r + N : r)];
+  };
+  float2 sum = make_float2(0.f, 0.f);
+  for (int ii = 0; ii < ni; ++ii) {
+    const int c = i0 + ii;
+    const float wu = kb_weight((float)((double)c - xu), a);
+    float2 col = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k <= KMAX; ++k) {
+      if (k >= nj) break;
+      const int r = j0 + k;
+      float2 g;
+      if (c > 0) g = at(r, c);
+      else if (c < 0) g = cconj(at(-r, -c));
+      else g = cadd(at(r, 0), cconj(at(-r, 0)));
+      col = make_float2(col.x + wv[k] * g.x, col.y + wv[k] * g.y);
+    }
+    sum = make_float2(sum.x + wu * col.x, sum.y + wu * col.y);
+  }
+  if (a.kdens != nullptr) sum = cscale(sum, 1.0f / (float)a.kdens[(size_t)li * a.B + j]);
+  float2 g = sum;
+  const int b = a.perm[tb + j];
+  if (a.sd != nullptr) g = rotate_phase(g, -a.sd[tb + j], a.freq[ch]);
+  const size_t vb = (size_t)img * a.B;
+  if (a.gains) {
+    a.vis_grad[vb + b] = cmul(cconj(baseline_gain(a, b)), g);
+    const float2 v = load_vis_raw(a, vb + b, ch);
+    a.gamma[(size_t)li * a.B + b] = cmul(g, cconj(v));
+  } else {
+    a.vis_grad[vb + b] = g;
   }
 }
 

@@ -184,13 +184,18 @@ def test_uniform_kernel_gridding_sizes_its_density_table(lib):
         lib.blink_workspace_size(ctypes.byref(_prob()), 1)
 
 
-def test_kernel_gridding_has_no_adjoint(lib):
-    p = _prob(kernel_support=6, kernel_beta=-1.0)
+def test_kernel_gridding_adjoint_sizes_its_column_buffer(lib):
+    # the adjoint with a gridding kernel passes validation, needs a workspace,
+    # and that workspace holds every transformed half-spectrum column of a
+    # chunk ([chunk][N/2][N] complex64) on top of the nearest-cell adjoint's
+    p = _prob(kernel_support=6, kernel_beta=-1.0, chunk_images=2)
     a = lib.blink_degrid_adjoint
-    assert a(ctypes.byref(p), ctypes.byref(_inputs()), FAKE, None, FAKE, None, None, 0, None) == E_UNSUP
-    # the same problem without the kernel passes validation (and then needs a workspace)
-    p0 = _prob()
+    assert a(ctypes.byref(p), ctypes.byref(_inputs()), FAKE, None, FAKE, None, None, 0, None) == E_WS
+    p0 = _prob(chunk_images=2)
     assert a(ctypes.byref(p0), ctypes.byref(_inputs()), FAKE, None, FAKE, None, None, 0, None) == E_WS
+    s_kb = lib.blink_workspace_size(ctypes.byref(p), 2)
+    s_nc = lib.blink_workspace_size(ctypes.byref(p0), 2)
+    assert s_kb - s_nc == 2 * 32 * 64 * 8
 
 
 def test_dynamic_spectra_validation(lib):

@@ -247,3 +247,81 @@ def test_autograd_with_rotation_and_cables():
     eg = rel_l2(gains.grad.cpu().numpy().view(np.float32), rg.view(np.float64))
     print(f"  rotated autograd vs oracle: vis {ev:.2e} gains {eg:.2e}", flush=True)
     assert ev <= 1e-5 and eg <= 1e-5
+
+
+# ------------------------------------------------------------ kernel gridding
+@pytest.mark.parametrize("name,support", [("subset64_gains", 6), ("allsky180_uniform", 4),
+                                          ("wide1024_gains", 6)])
+def test_kernel_gridding_adjoint_vs_oracle(name, support):
+    """Degridding with the Kaiser-Bessel kernel (and its correction, 1/W and
+    the gains): vis and gain gradients against the oracle's kernel adjoint."""
+    from oracle import kernel_gridding as kg
+    w, use_g = _case(name)
+    d = inputs(w, with_gains=use_g)
+    rng = np.random.default_rng(31)
+    gbar = torch.from_numpy(rng.normal(size=(w.n_img, w.out_n, w.out_n)).astype(np.float32)).to(device())
+    g = d.get("gains")
+    kw = dict(grid_n=w.grid_n, pixscale=w.pixscale, out_n=w.out_n, weighting=w.weighting, norm=w.norm,
+              flags=d["flags"], gains=g, ant1=d.get("ant1"), ant2=d.get("ant2"), kernel_support=support)
+    vg, gg = blink.degrid_adjoint(gbar, d["vis"], d["uvw_m"], d["freq_hz"], **kw)
+    torch.cuda.synchronize()
+    rv, rg = kg.adjoint_batch_conv(gbar.cpu().numpy().astype(np.float64), d["vis"].cpu().numpy(), w.uvw_m,
+                                   w.freq_hz, w.grid_n, w.pixscale, w.norm, support, None, w.flags,
+                                   w.gains if use_g else None, w.ant1, w.ant2, weighting=w.weighting)
+    e = rel_l2(vg.cpu().numpy().view(np.float32), rv.view(np.float64))
+    print(f"  kernel adjoint vis_grad rel-L2 {e:.2e}", flush=True)
+    assert e <= 1e-5
+    if use_g:
+        eg = rel_l2(gg.cpu().numpy().view(np.float32), rg.view(np.float64))
+        print(f"  kernel adjoint gain_grad rel-L2 {eg:.2e}", flush=True)
+        assert eg <= 1e-5
+    # the forward call's weight sums give the same gradients to rounding
+    ws = torch.empty(w.n_img, dtype=torch.float32, device=device())
+    blink.image_batch(d["vis"], d["uvw_m"], d["freq_hz"], weight_sum=ws, **kw)
+    vg2, _ = blink.degrid_adjoint(gbar, d["vis"], d["uvw_m"], d["freq_hz"], weight_sum=ws, **kw)
+    torch.cuda.synchronize()
+    assert rel_l2(vg2.cpu().numpy().view(np.float32), vg.cpu().numpy().view(np.float32)) <= 1e-6
+
+
+def test_kernel_gridding_adjoint_dot_product_on_gpu():
+    w = synth.widefield(n_time=1, n_chan=2, chan_stride=200)
+    w.weighting = 1
+    d = inputs(w)
+    kw = dict(grid_n=w.grid_n, pixscale=w.pixscale, out_n=w.out_n, weighting=w.weighting, norm=w.norm,
+              kernel_support=6)
+    img = blink.image_batch(d["vis"], d["uvw_m"], d["freq_hz"], **kw)
+    rng = np.random.default_rng(5)
+    gbar = torch.from_numpy(rng.normal(size=img.shape).astype(np.float32)).to(device())
+    vg, _ = blink.degrid_adjoint(gbar, d["vis"], d["uvw_m"], d["freq_hz"], **kw)
+    lhs = (img.double() * gbar.double()).sum().item()
+    v = d["vis"]
+    rhs = (vg.real.double() * v.real.double() + vg.imag.double() * v.imag.double()).sum().item()
+    assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), 1e-30)
+
+
+def test_autograd_with_kernel_gridding():
+    from oracle import kernel_gridding as kg
+    w, _ = _case("subset64_gains")
+    d = inputs(w, with_gains=True)
+    vis = d["vis"].clone().requires_grad_(True)
+    gains = d["gains"].clone().requires_grad_(True)
+    rng = np.random.default_rng(10)
+    target = torch.from_numpy(rng.normal(size=(w.n_img, w.out_n, w.out_n)).astype(np.float32)).to(device())
+    img = blink.blink_image(vis, gains, d["uvw_m"], d["freq_hz"], d["ant1"], d["ant2"], grid_n=w.grid_n,
+                            pixscale=w.pixscale, out_n=w.out_n, weighting=w.weighting, norm=w.norm,
+                            flags=d["flags"], kernel_support=5)
+    # (default beta: a much smaller one puts a near-zero of the correction
+    # at the edge of this full-field 64^2 image, where dividing by it then
+    # magnifies FP32 rounding of the uncorrected pixels)
+    ((img - target) ** 2).sum().backward()
+    vnp = d["vis"].cpu().numpy()
+    ref, _ = kg.image_batch_conv(vnp, w.uvw_m, w.freq_hz, w.grid_n, w.pixscale, w.out_n, w.norm, 5, None,
+                                 w.flags, w.gains, w.ant1, w.ant2, weighting=w.weighting)
+    assert rel_l2(img.detach().cpu().numpy(), ref) <= 1e-5
+    rv, rg = kg.adjoint_batch_conv(2 * (ref - target.cpu().numpy()), vnp, w.uvw_m, w.freq_hz, w.grid_n,
+                                   w.pixscale, w.norm, 5, None, w.flags, w.gains, w.ant1, w.ant2,
+                                   weighting=w.weighting)
+    ev = rel_l2(vis.grad.cpu().numpy().view(np.float32), rv.view(np.float64))
+    eg = rel_l2(gains.grad.cpu().numpy().view(np.float32), rg.view(np.float64))
+    print(f"  kernel autograd vs oracle: vis {ev:.2e} gains {eg:.2e}", flush=True)
+    assert ev <= 1e-5 and eg <= 1e-5
