@@ -31,8 +31,9 @@
  *
  * Geometry and the readings of the paper used throughout
  * ------------------------------------------------------
- * - uvw_m[t][b] = (u, v, w) of baseline b at timestep t in metres; w is
- *   ignored (coplanar array phased to zenith, Sec. 4.3 Eq. 5).
+ * - uvw_m[t][b] = (u, v, w) of baseline b at timestep t in metres; w enters
+ *   only the phase rotation and the re-projection below (otherwise the array
+ *   is imaged as coplanar, phased to zenith, Sec. 4.3 Eq. 5).
  * - Cells per metre of channel c: s_c = (freq_hz[c] * (N * pixscale)) / c0 with
  *   c0 = 299792458 m/s, evaluated in IEEE double in that order (Eq. 9 gives
  *   the cell du = 1/(N dx) wavelengths; Sec. 5.2.4 computes the channel
