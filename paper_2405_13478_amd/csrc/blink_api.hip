@@ -978,10 +978,10 @@ blink_status blink_dynamic_spectra(const float* images, int32_t n_time, int32_t 
   const bool vec = n_pix % 4 == 0 && n_time % 4 == 0 && ((uintptr_t)images % 16) == 0 &&
                    ((uintptr_t)spectra % 16) == 0;
   if (vec)
-    hipLaunchKernelGGL((k_dynspec<true>), g, dim3(DS_THREADS), dynspec_lds(k), st, images, (int)n_time,
+    hipLaunchKernelGGL((k_dynspec<true>), g, dim3(DS_THREADS), dynspec_lds(k, n_time), st, images, (int)n_time,
                        (int)n_chan, (long long)n_pix, (int)ref_mode, k, ref_image, spectra, (int)npt8);
   else
-    hipLaunchKernelGGL((k_dynspec<false>), g, dim3(DS_THREADS), dynspec_lds(k), st, images, (int)n_time,
+    hipLaunchKernelGGL((k_dynspec<false>), g, dim3(DS_THREADS), dynspec_lds(k, n_time), st, images, (int)n_time,
                        (int)n_chan, (long long)n_pix, (int)ref_mode, k, ref_image, spectra, (int)npt8);
   return launched();
 }

@@ -1566,11 +1566,14 @@ __global__ void __launch_bounds__(RowsHalf<N>::THREADS) k_rows_half(ImgArgs a) {
 constexpr int DS_TT = 128, DS_PP = 64, DS_THREADS = 256, DS_KMAX = 128;
 constexpr int DS_ST = DS_PP + 1;                              // LDS row stride (floats)
 
-// One LDS buffer of DS_TT + K rows: the differences overwrite the tile's own
-// rows once every thread has read its window, and the stores read them back
-// column-wise (the odd stride keeps both directions off a single bank).
-__host__ __device__ constexpr size_t dynspec_lds(int k) {
-  return (size_t)(DS_TT + k) * DS_ST * sizeof(float);
+// One LDS buffer of min(DS_TT, T) + K rows (a series shorter than a tile
+// needs fewer rows, so more workgroups share a CU): the differences overwrite
+// the tile's own rows once every thread has read its window, and the stores
+// read them back column-wise (the odd stride keeps both directions off a
+// single bank). Rows at or beyond T are never read or written.
+__host__ __device__ constexpr int dynspec_rows(int t) { return t < DS_TT ? t : DS_TT; }
+__host__ __device__ constexpr size_t dynspec_lds(int k, int t) {
+  return (size_t)(dynspec_rows(t) + k) * DS_ST * sizeof(float);
 }
 
 template <bool VEC>
@@ -1589,7 +1592,7 @@ __global__ void __launch_bounds__(DS_THREADS) k_dynspec(const float* __restrict_
   const int t0 = tt * DS_TT;
   if (p0 >= P || t0 >= T) return;                             // padding of the pixel tiles to 8
   const int r0 = t0 - K;                                      // first row held (may be < 0)
-  const int nrows = DS_TT + K;
+  const int nrows = dynspec_rows(T) + K;
   if constexpr (VEC) {
     constexpr int Q = DS_PP / 4;                              // float4 per row
     constexpr int MAXI = (DS_TT + DS_KMAX) * Q / DS_THREADS;
@@ -1628,7 +1631,7 @@ __global__ void __launch_bounds__(DS_THREADS) k_dynspec(const float* __restrict_
   const float rv = (mode == 2 && p0 + j < P) ? ref[(long long)c * P + p0 + j] : 0.0f;
   double win = 0.0;                                           // sum of the k preceding images
   const int ta = t0 + g * SEG;
-  if (mode == 1) {
+  if (mode == 1 && ta < T) {
     const int k = min(K, ta);
     for (int s = ta - k; s < ta; ++s) win += (double)rows[(s - r0) * DS_ST + j];
   }
@@ -1636,26 +1639,29 @@ __global__ void __launch_bounds__(DS_THREADS) k_dynspec(const float* __restrict_
 #pragma unroll
   for (int i = 0; i < SEG; ++i) {
     const int t = ta + i;
-    const float x = rows[(t - r0) * DS_ST + j];
-    float d;
-    if (mode == 0) {
-      d = x;
-    } else if (mode == 2) {
-      d = x - rv;
-    } else {
-      // mean of the window: 1/k is exact for k a power of two and within an
-      // ulp of double otherwise, far below the final rounding to float
-      const int k = min(K, t);
-      d = t == 0 ? 0.0f : (float)((double)x - win * (1.0 / (double)k));
-      // slide the window to end at t: add x, drop the image K behind
-      win += (double)x;
-      if (t - K >= 0) win -= (double)rows[(t - K - r0) * DS_ST + j];
+    float d = 0.0f;
+    if (t < T) {                                              // rows from T on are not held
+      const float x = rows[(t - r0) * DS_ST + j];
+      if (mode == 0) {
+        d = x;
+      } else if (mode == 2) {
+        d = x - rv;
+      } else {
+        // mean of the window: 1/k is exact for k a power of two and within an
+        // ulp of double otherwise, far below the final rounding to float
+        const int k = min(K, t);
+        d = t == 0 ? 0.0f : (float)((double)x - win * (1.0 / (double)k));
+        // slide the window to end at t: add x, drop the image K behind
+        win += (double)x;
+        if (t - K >= 0) win -= (double)rows[(t - K - r0) * DS_ST + j];
+      }
     }
     dv[i] = d;
   }
   __syncthreads();                                            // every window has been read
 #pragma unroll
-  for (int i = 0; i < SEG; ++i) rows[(ta + i - r0) * DS_ST + j] = dv[i];
+  for (int i = 0; i < SEG; ++i)
+    if (ta + i < T) rows[(ta + i - r0) * DS_ST + j] = dv[i];
   __syncthreads();
   if constexpr (VEC) {
     constexpr int Q = DS_TT / 4;                              // float4 per pixel series
