@@ -211,12 +211,13 @@ def summarize(out_dir):
     cw, _ = _counter_mean(cwr, "copyBuffer", "WRITE_SIZE")
     f_fetch = copy_bytes / (cf * 1024.0)
     f_write = copy_bytes / (cw * 1024.0)
-    imgs = 512
+    _, n_launch = _counter_mean(fe, KERNEL_KEYS["grid_cols"], "FETCH_SIZE")
+    imgs = 10 * 768 // max(n_launch, 1)          # the counter runs image 10 timesteps x 768 channels
     sys.path.insert(0, ROOT)
     from paper_2405_13478_amd import synth
     ncz = float(nonzero_columns(synth.widefield(n_time=10, n_chan=768), slice(0, 10)).mean())
     alg = {"grid_cols": 8128 * 8 + ncz * 512 * 8, "rows": ncz * 512 * 8 + 512 * 512 * 4}
-    res = {"workload": "widefield 1024^2 -> 512^2, 8128 baselines, 512 images per launch",
+    res = {"workload": f"widefield 1024^2 -> 512^2, 8128 baselines, {imgs} images per launch",
            "csrc_digest": digest, "copy_calibration": {"bytes": copy_bytes, "FETCH_SIZE_KiB": cf,
                                                       "WRITE_SIZE_KiB": cw, "fetch_scale": f_fetch,
                                                       "write_scale": f_write},
@@ -308,7 +309,9 @@ def _roofline(blink, acc_ms, acc_n, per_image, imgs_timed, digest_ok_kernel=None
     traffic = None
     if digest_ok_kernel and os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("csrc_digest") == _csrc_digest() and name in tr.get("kernels", {}):
+        ipl = imgs_timed / max(acc_n[dom], 1)
+        if (tr.get("csrc_digest") == _csrc_digest() and name in tr.get("kernels", {})
+                and abs(tr["kernels"][name].get("images_per_launch", 0) - ipl) < 0.5):
             traffic = tr["kernels"][name].get("hbm_bytes_per_launch")
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

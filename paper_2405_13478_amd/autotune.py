@@ -5,7 +5,8 @@ column kernel, the persistent row-pass grid size and the images per chunk -
 are timed on synthetic inputs of the target shape (HIP events, median of a
 few calls): first every tile width x row grid at the default chunk, then the
 chunk sizes at the best of those (a smaller chunk keeps the half-spectrum
-intermediate resident in the 256 MB Infinity Cache between the two passes).
+intermediate resident in the 256 MB Infinity Cache between the two passes, a
+larger one means fewer, longer launches with less time in their tails).
 The fastest combination is stored under a key of the shape (grid size,
 cutout, baselines, weighting, storage type). image_batch looks
 the key up when the caller leaves a tunable unset.
@@ -24,7 +25,10 @@ _cache = None
 
 COLS_PER_WG = (2, 4, 8)
 ROWS_WG = (0, 512, 1024, 2048)
-CHUNKS = (0, 16, 32, 64, 128, 256)
+# images per chunk besides the default: small ones keep the half spectrum in
+# the Infinity Cache, large ones (several GiB of half spectrum) shorten the
+# launch tails; chunks beyond the cube's image count are skipped
+CHUNKS = (0, 16, 32, 64, 128, 256, 1024, 1536, 2048, 3072)
 
 
 def key(grid_n, out_n, n_bl, weighting, vis_type) -> str:
@@ -67,7 +71,7 @@ def tune_workload(w, vis, uvw, freq, flags=None, vis_scale=None, steps=5, candid
     else:
         run(itertools.product(COLS_PER_WG, ROWS_WG, (0,)))
         b = min(results, key=lambda r: r["ms"])
-        run((b["cols_per_wg"], b["rows_wg"], c) for c in CHUNKS if c != 0)
+        run((b["cols_per_wg"], b["rows_wg"], c) for c in CHUNKS if c != 0 and c < n_img)
     best = min(results, key=lambda r: r["ms"])
     return {**best, "key": key(w.grid_n, M, w.n_bl, w.weighting, vt)}, results
 
