@@ -27,8 +27,8 @@ COLS_PER_WG = (2, 4, 8)
 ROWS_WG = (0, 512, 1024, 2048)
 # images per chunk besides the default: small ones keep the half spectrum in
 # the Infinity Cache, large ones (several GiB of half spectrum) shorten the
-# launch tails; chunks beyond the cube's image count are skipped
-CHUNKS = (0, 16, 32, 64, 128, 256, 1024, 1536, 2048, 3072)
+# launch tails; chunks beyond the call's image count are skipped
+CHUNKS = (0, 16, 32, 64, 128, 256, 384, 512, 768, 1024, 1536, 2048, 3072)
 
 
 def key(grid_n, out_n, n_bl, weighting, vis_type) -> str:
@@ -71,7 +71,7 @@ def tune_workload(w, vis, uvw, freq, flags=None, vis_scale=None, steps=5, candid
     else:
         run(itertools.product(COLS_PER_WG, ROWS_WG, (0,)))
         b = min(results, key=lambda r: r["ms"])
-        run((b["cols_per_wg"], b["rows_wg"], c) for c in CHUNKS if c != 0 and c < n_img)
+        run((b["cols_per_wg"], b["rows_wg"], c) for c in CHUNKS if c != 0 and c <= n_img)
     best = min(results, key=lambda r: r["ms"])
     return {**best, "key": key(w.grid_n, M, w.n_bl, w.weighting, vt)}, results
 
