@@ -410,6 +410,15 @@ __host__ __device__ constexpr int last_stage_ns(int n) {
   while (n / cur / pick_radix(n / cur) > 1) cur *= pick_radix(n / cur);
   return cur;
 }
+// Compact last stage: when the plan ends in a radix-4 stage after NS > 1
+// points, only its r = 1 twiddles w^k are kept (a prefix of the table) and
+// w^2k, w^3k are formed from them in registers. Saves 2 NS table entries.
+__host__ __device__ constexpr bool compact_last(int n) {
+  return last_stage_ns(n) > 1 && pick_radix(n / last_stage_ns(n)) == 4;
+}
+__host__ __device__ constexpr int tw_entries_compact(int n) {
+  return compact_last(n) ? tw_entries_before(n, last_stage_ns(n)) + last_stage_ns(n) : tw_entries(n);
+}
 // True when every emitted block q = QB + lane of the last stage starts at a
 // multiple of the wavefront width and has all lanes active.
 __host__ __device__ constexpr bool blocks_aligned(int n) {
@@ -464,7 +473,7 @@ __host__ __device__ constexpr bool plan_even(int n) {
 }
 
 // Twiddle and DFT of the butterflies held in registers (no LDS traffic).
-template <int N, int R, int NS, int SIGN, int ZB = 0>
+template <int N, int R, int NS, int SIGN, int ZB = 0, bool CL = false>
 __device__ __forceinline__ void stage_compute(int lane, const float2* __restrict__ tw,
                                               float2 (&v)[(N / R + WAVE - 1) / WAVE][R]) {
   static_assert(ZB == 0 || NS == 1, "a zero band only on the first stage's inputs");
@@ -477,11 +486,20 @@ __device__ __forceinline__ void stage_compute(int lane, const float2* __restrict
       if constexpr (NS > 1) {
         constexpr int TW0 = tw_entries_before(N, NS);
         const float2* t1 = tw + TW0 + j % NS;
+        if constexpr (CL && NS * R == N && R == 4) {      // compact last stage
+          float2 w1 = t1[0];
+          if (SIGN < 0) w1.y = -w1.y;
+          const float2 w2 = cmul(w1, w1);
+          v[p][1] = cmul(v[p][1], w1);
+          v[p][2] = cmul(v[p][2], w2);
+          v[p][3] = cmul(v[p][3], cmul(w1, w2));
+        } else {
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          float2 w = t1[(r - 1) * NS];
-          if (SIGN < 0) w.y = -w.y;
-          v[p][r] = cmul(v[p][r], w);
+          for (int r = 1; r < R; ++r) {
+            float2 w = t1[(r - 1) * NS];
+            if (SIGN < 0) w.y = -w.y;
+            v[p][r] = cmul(v[p][r], w);
+          }
         }
       }
       dft<R, SIGN, ZB>(v[p]);
@@ -565,13 +583,14 @@ __host__ __device__ constexpr int zero_band(int n, int bound) {
 // The stages from NS on, given the stage's inputs in v; the last stage hands
 // its outputs to emit(ic<QB>, X) as stockham_last_emit does.
 // ZB: zero band of the first stage's inputs (NS = 1 only; see zero_band).
-template <int N, int SIGN, int NS, int ZB = 0, class Emit>
+// CL: the table is compact in its last stage (tw_entries_compact).
+template <int N, int SIGN, int NS, int ZB = 0, bool CL = false, class Emit>
 __device__ __forceinline__ void half_chain(float2* hbuf, int lane, const float2* __restrict__ tw,
                                            float2 (&v)[(N / pick_radix(N / NS) + WAVE - 1) / WAVE][pick_radix(N / NS)],
                                            Emit&& emit) {
   constexpr int R = pick_radix(N / NS);
   constexpr int PER = (N / R + WAVE - 1) / WAVE;
-  stage_compute<N, R, NS, SIGN, ZB>(lane, tw, v);
+  stage_compute<N, R, NS, SIGN, ZB, CL>(lane, tw, v);
   if constexpr (NS * R == N) {
     static_for<0, PER>([&](auto pc) {
       constexpr int p = decltype(pc)::value;
@@ -593,7 +612,7 @@ __device__ __forceinline__ void half_chain(float2* hbuf, int lane, const float2*
     wave_sync();
     half_read<N, R2, 1>(hbuf, lane, v2);
     wave_sync();
-    half_chain<N, SIGN, NS * R>(hbuf, lane, tw, v2, emit);
+    half_chain<N, SIGN, NS * R, 0, CL>(hbuf, lane, tw, v2, emit);
   }
 }
 
@@ -607,11 +626,11 @@ struct HalfIn {
 
 // ZB: the zero band of the first stage's inputs (see zero_band; the inputs in
 // it need not have been read into `in`), 0 for none.
-template <int N, int SIGN, int ZB = 0, class Emit>
+template <int N, int SIGN, int ZB = 0, bool CL = false, class Emit>
 __device__ __forceinline__ void wave_fft_half_emit(float2* hbuf, int lane, const float2* __restrict__ tw,
                                                    HalfIn<N>& in, Emit&& emit) {
   static_assert(plan_even(N), "half-length exchange needs even radices");
-  half_chain<N, SIGN, 1, ZB>(hbuf, lane, tw, in.v, emit);
+  half_chain<N, SIGN, 1, ZB, CL>(hbuf, lane, tw, in.v, emit);
 }
 
 template <int N, int SIGN, int NS = 1>

@@ -895,11 +895,13 @@ __global__ void __launch_bounds__(DENS_WAVES * WAVE) k_kb_density(ImgArgs a) {
 template <int N>
 struct TwLds { static constexpr bool ON = N <= 1024; };
 
-template <int N>
+// CL: copy only the compact table (tw_entries_compact), for transforms that
+// form the last stage's higher twiddle powers in registers.
+template <int N, bool CL = false>
 __device__ __forceinline__ const float2* stage_twiddles(float2* lds_tw) {
   if constexpr (TwLds<N>::ON) {
     const float2* g = TwTable<N>::stages();
-    constexpr int NTW = tw_entries(N);
+    constexpr int NTW = CL ? tw_entries_compact(N) : tw_entries(N);
     for (int i = threadIdx.x; i < NTW; i += blockDim.x) lds_tw[i] = g[i];
     return lds_tw;      // visible after the caller's next __syncthreads
   } else {
@@ -1066,7 +1068,10 @@ template <int N, int CPW, bool UNI>
 struct ColsHalf {
   static constexpr int STRIDE = padded_len(N / 2);
   static constexpr int THREADS = CPW * WAVE;
-  static constexpr int TW = TwLds<N>::ON ? tw_entries(N) : 0;
+  // compact twiddle table in LDS: at N = 1024 and 4 columns per workgroup
+  // 22.5 KB instead of 26.6 KB, so seven workgroups share a CU instead of six
+  static constexpr bool CL = TwLds<N>::ON && compact_last(N);
+  static constexpr int TW = TwLds<N>::ON ? tw_entries_compact(N) : 0;
   static constexpr size_t LDS = (size_t)(CPW * STRIDE + TW) * sizeof(float2) +
                                 (UNI ? (size_t)CPW * (N / 2) * sizeof(int) : 0) +
                                 (size_t)CPW * CLAIM_SLOTS * sizeof(unsigned);
@@ -1211,7 +1216,7 @@ __global__ void __launch_bounds__((ColsHalf<N, CPW, UNI>::THREADS)) k_grid_cols_
   int* hcnt = UNI ? lcnt + wave * H : nullptr;
   unsigned* lclaim = reinterpret_cast<unsigned*>(lcnt + (UNI ? CPW * H : 0));
   const double s = cells_per_metre(a.freq[ch], a.ndx);
-  const float2* tw = stage_twiddles<N>(ltw);
+  const float2* tw = stage_twiddles<N, C_::CL>(ltw);
   // the only workgroup barrier: it publishes the LDS twiddles; after it every
   // wavefront grids and transforms its column without waiting for the others
   if (TwLds<N>::ON) __syncthreads();
@@ -1247,7 +1252,7 @@ __global__ void __launch_bounds__((ColsHalf<N, CPW, UNI>::THREADS)) k_grid_cols_
       // v-frequency q = (m - M/2) mod N
       float2* dst = a.half + ((size_t)li * H + col) * a.M;
       const int hm = HMC > 0 ? HMC : a.M / 2;
-      wave_fft_half_emit<N, +1, ZB>(hbuf, lane, tw, in, [&](auto qb, float2 v) {
+      wave_fft_half_emit<N, +1, ZB, C_::CL>(hbuf, lane, tw, in, [&](auto qb, float2 v) {
         cutout_block<N, decltype(qb)::value>(lane, hm, [&](unsigned m) { store_at(dst, m, v); });
       });
     }
